@@ -1,0 +1,194 @@
+/*
+ * mrab.h -- C ABI of libmrab.so: SBP-SAT right-hand side of the compressible
+ * Navier-Stokes equations on overlapping structured grids, advanced by the
+ * multi-rate Adams-Bashforth (MRAB) scheme, on one AMD MI355X (gfx950) GPU.
+ *
+ * Method: Mikida, Kloeckner, Bodony, "Multi-Rate Time Integration on Overset
+ * Meshes" (arXiv 1805.06607).  Each declaration names the passage that defines
+ * the operation.
+ *
+ * Conventions
+ *  - Every call returns an mr_status (0 = MR_OK) and never throws.  After an
+ *    error, mr_last_error(ctx) describes it.
+ *  - Grid point p = i + nx*(j + ny*k) (x fastest).  A state or right-hand side
+ *    is structure-of-arrays: nv x npts doubles (nv = dim + 2: rho, rho*u_i,
+ *    rho*E), variable-major.
+ *  - Host arrays passed in are copied during the call; the caller keeps them.
+ *  - Device pointers (states, right-hand sides, the workspace) are borrowed
+ *    from the caller and must stay valid until the stream is synchronised.
+ *  - All device work is enqueued on the HIP stream given to mr_create; calls
+ *    marked "async" do not synchronise the host.  Setup calls may synchronise.
+ *  - The library never allocates device memory: mr_finalize reports the
+ *    workspace size and the caller binds one buffer with mr_bind_workspace.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef MRAB_H
+#define MRAB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mr_ctx mr_ctx;
+
+typedef enum {
+    MR_OK = 0,
+    MR_ERR_ARG = -1,          /* invalid argument (null pointer, bad size or flag) */
+    MR_ERR_STATE = -2,        /* call out of order (e.g. mr_rhs before binding) */
+    MR_ERR_SETUP = -3,        /* invalid geometry: short run, missing donor, bad rate */
+    MR_ERR_HIP = -4,          /* a HIP runtime call failed */
+    MR_ERR_NONFINITE = -5,    /* the state guard found a NaN/Inf */
+    MR_ERR_UNSUPPORTED = -6   /* valid but not implemented (e.g. 3D curvilinear) */
+} mr_status;
+
+enum { MR_SBP_21 = 21, MR_SBP_42 = 42 };
+enum { MR_BC_PERIODIC = 0, MR_BC_INTERFACE = 1, MR_BC_FARFIELD = 2, MR_BC_WALL = 3 };
+enum { MR_CARTESIAN = 0, MR_CURVILINEAR = 1 };
+
+/* Scheme and physics parameters.
+ *  sbp            MR_SBP_21 or MR_SBP_42: diagonal-norm SBP first-derivative
+ *                 operator (section "The Compressible Navier-Stokes Equations on
+ *                 Overset Meshes"); second derivatives apply it twice.
+ *  order, hist_len  AB order n and history length m >= n (m > n: the
+ *                 extended-history, minimum-norm schemes of eq. ext_ab).
+ *  interp_width   donor stencil width per direction (2 bilinear, 4 cubic);
+ *                 informational, the weights come with mr_set_overset.
+ *  gamma, Re, Pr, mu, lambda_over_mu  gas constants; T = p/rho,
+ *                 c_p = gamma/(gamma-1), tau_ij as in the Appendix equations.
+ *  sigma_I_iface  sigma^I of the SAT interface penalty, eq. (int) (1/2).
+ *  sigma_I_bc     sigma^I of the far-field and wall penalties.
+ *  T_wall         isothermal wall temperature.
+ *  wall_visc      wall no-slip penalty factor: sigma = wall_visc*mu*|grad k|^2/Re.
+ *  q_inf          far-field target state (nv values).
+ *  cfl, dt_fixed  macrostep H = cfl * min over grids of rate * min_pt dt_pt
+ *                 (eq. ts_inv, ts_visc, ts_overall) unless dt_fixed > 0.
+ */
+typedef struct {
+    int dim;
+    int sbp;
+    int order, hist_len;
+    int interp_width;
+    double gamma, Re, Pr, mu, lambda_over_mu;
+    double sigma_I_iface, sigma_I_bc, T_wall, wall_visc;
+    double q_inf[5];
+    double cfl, dt_fixed;
+} mr_params;
+
+/* One structured grid.
+ *  n[d], periodic[d]   points and periodicity per direction (n[2] = 1 in 2D)
+ *  kind                MR_CARTESIAN (origin, spacing) or MR_CURVILINEAR (coords)
+ *  coords              host, dim x npts, curvilinear only (2D)
+ *  coord_period[d][c]  jump of coordinate c across the seam of periodic
+ *                      direction d (0 for grids whose coordinates wrap)
+ *  iblank              host, npts, 1 active / 0 hole; NULL = all active
+ *  face_bc[2d+s]       boundary flag of face s (0: min, 1: max) of direction d
+ *  rate                right-hand-side evaluations per macrostep (r_l); every
+ *                      rate must divide the largest one
+ */
+typedef struct {
+    int n[3];
+    int periodic[3];
+    int kind;
+    double origin[3], spacing[3];
+    const double *coords;
+    double coord_period[3][3];
+    const int8_t *iblank;
+    int face_bc[6];
+    int rate;
+} mr_grid_desc;
+
+/* Create a context.  hip_stream: a hipStream_t (NULL = default stream). */
+int mr_create(const mr_params *params, void *hip_stream, mr_ctx **out);
+
+/* Add a grid; grid ids are 0, 1, ... in call order.  Splits every grid line
+ * into runs of active points (closures at run ends, SAT faces at run ends:
+ * the face's flag at grid faces, interface next to holes).
+ * Errors: MR_ERR_ARG (bad sizes/flags), MR_ERR_SETUP (a run shorter than two
+ * closures), MR_ERR_UNSUPPORTED (3D curvilinear). */
+int mr_add_grid(mr_ctx *ctx, const mr_grid_desc *desc, int *grid_id);
+
+/* Donor stencils of the receivers of recv_grid that take their data from
+ * donor_grid (section "SAT-Based Interpolation": Lagrange interpolation of
+ * donor data).  recv_pt[n]: receiver points (each an active point that ends a
+ * run on an interface face); donor_pt[n*S], weights[n*S]: S = width^dim donor
+ * points and weights per receiver.  May be called several times per pair.
+ * Errors: MR_ERR_ARG (index out of range), MR_ERR_SETUP (donor point blanked). */
+int mr_set_overset(mr_ctx *ctx, int recv_grid, int donor_grid, int64_t n, int stencil_size,
+                   const int64_t *recv_pt, const int64_t *donor_pt, const double *weights);
+
+/* Validate (every interface run end has exactly one donor stencil, every rate
+ * divides the largest), build the device tables and the static rate schedule,
+ * and report the workspace size in bytes. */
+int mr_finalize(mr_ctx *ctx, size_t *workspace_bytes);
+
+/* Bind caller-owned device memory (>= the reported size, 256-byte aligned),
+ * upload the tables, compute metric terms on the device. */
+int mr_bind_workspace(mr_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Copy a grid state (device, nv x npts) into / out of the context (async). */
+int mr_set_state(mr_ctx *ctx, int grid, const double *dev_q);
+int mr_get_state(mr_ctx *ctx, int grid, double *dev_q_out);
+
+/* One coupled right-hand side of all grids at a common time (async):
+ * donor data gathered from dev_q of the donor grids, then per grid the
+ * SBP-SAT right-hand side (eq. int and the Appendix equations) into
+ * dev_dqdt[g] (nv x npts; 0 at holes).  dev_q[g] and dev_dqdt[g] are device
+ * pointers, one per grid, and must not alias. */
+int mr_rhs(mr_ctx *ctx, double t, const double *const *dev_q, double *const *dev_dqdt);
+
+/* Donor data of the receivers of grid g from the given donor states (async):
+ * out (device) receives, per receiver, q_hat (nv) then F_hat^V_j (nv-1 each,
+ * j = 0..dim-1).  For parity tests of the interpolation step. */
+int mr_receiver_data(mr_ctx *ctx, int grid, const double *const *dev_q, double *dev_out);
+int mr_num_receivers(const mr_ctx *ctx, int grid, int64_t *n);
+
+/* Timestep (setup; synchronises): per-point estimate eq. (ts_visc) on the
+ * current states, H = cfl * min_g rate_g * min_pt dt (or dt_fixed),
+ * h = H / r_max.  Fixes H for the run. */
+int mr_timestep(mr_ctx *ctx, double *h, double *H);
+
+/* Bootstrap (section "Adams-Bashforth Integration"): single-rate RK at
+ * h = H / r_max (Heun RK3 for order <= 3, classic RK4 for order 4) for
+ * (m-1)*r_max steps from the current states at time t0, keeping F(y_n) at each
+ * grid's history nodes; then stages the first own step of every grid. */
+int mr_mrab_start(mr_ctx *ctx, double t0);
+
+/* nsteps macrosteps of MRAB, fastest first, no re-extrapolation (section
+ * "Multi-rate Adams-Bashforth Integration", Steps 1-7, generalised to nested
+ * integer rates).  Async. */
+int mr_mrab_macrostep(mr_ctx *ctx, int nsteps);
+
+/* Copy history value j (0 = oldest .. hist_len-1 = newest right-hand side of
+ * grid g, the values the AB combination of eq. ab_general weights) into
+ * dev_out (nv x npts, async).  For checkpoints and tests. */
+int mr_get_history(mr_ctx *ctx, int grid, int j, double *dev_out);
+
+/* Current time and completed macrosteps. */
+int mr_time(const mr_ctx *ctx, double *t, int64_t *macrosteps);
+
+/* AB coefficients (host, pure): alpha_j, j = 0..hist_len-1 oldest first, for
+ * history nodes -(m-1)..0 in units of the step and target offset tau in (0,1]
+ * (eq. vandermonde; minimum norm when hist_len > order, eq. ext_ab). */
+int mr_ab_coeffs(int order, int hist_len, double tau, double *out);
+
+/* Per-launch timing of one grid's fused right-hand-side kernel with HIP events
+ * recorded on the context's stream (max_events launches are recorded; 0
+ * disables).  mr_kernel_time synchronises and returns the summed duration and
+ * the number of timed launches since the last enable. */
+int mr_kernel_timing(mr_ctx *ctx, int grid, int max_events);
+int mr_kernel_time(mr_ctx *ctx, double *total_ms, int *count);
+
+/* Non-finite guard: synchronises, returns MR_ERR_NONFINITE if any state holds
+ * a NaN or Inf, and the largest |q| in *maxabs. */
+int mr_guard(mr_ctx *ctx, double *maxabs);
+
+const char *mr_last_error(const mr_ctx *ctx);
+void mr_destroy(mr_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRAB_H */

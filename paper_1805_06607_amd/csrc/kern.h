@@ -1,0 +1,90 @@
+// Device-side descriptors and launch entry points shared by the host runtime
+// (runtime.cpp) and the gfx950 kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mrk {
+
+constexpr int MAXG = 8;     // grids per context
+constexpr int MAXH = 8;     // history length
+
+// Class byte of a point along one direction:
+//   bits 0-3  row: 0 interior, 1..4 left closure row 0..3, 5..8 right closure row 0..3, 15 hole
+//   bits 4-5  SAT face flag at run ends (left row 0 / right row 0): 1 interface, 2 far-field, 3 wall
+constexpr int CLS_HOLE = 15;
+
+struct GridDev {
+    int dim, nv;
+    int n[3];
+    int periodic[3];
+    int64_t stride[3];
+    int64_t npts;
+    int cartesian;
+    double inv_h[3];          // Cartesian grids: 1 / spacing
+    const double *metric;     // curvilinear: (dim*dim + 1) x npts, M[m*dim+j] = J^-1 dxi_m/dx_j, then J
+    const int8_t *cls;        // dim x npts class bytes
+    const int32_t *recv_idx;  // per point: receiver row or -1 (null: no receivers)
+    const double *recv;       // receiver rows: q_hat (nv), F_hat^V_j (nv-1 each)
+};
+
+struct Phys {
+    double gamma, Re, Pr, mu, lam;
+    double sig_iface, sig_bc, T_wall, wall_visc;
+    double q_inf[5];
+    double p0inv;
+};
+
+// y_next = y + sum_j c[j] * F_j (j = 0 oldest .. m-1 newest); F_{m-1} is the
+// right-hand side computed by the same kernel when fused.
+struct Combine {
+    int m;
+    double c[MAXH];
+    const double *hist[MAXH];
+    double *y_next;
+};
+
+// state source of a donor grid: y, or y + sum_j beta[j] F_j when the grid is mid-step
+struct StateSrc {
+    const double *y;
+    int mid;
+    int m;
+    double beta[MAXH];
+    const double *hist[MAXH];
+};
+
+struct Phys;
+struct DonorLaunch {
+    const GridDev *grids;      // device array of all grid descriptors
+    StateSrc src[MAXG];
+    double *out[MAXG];         // receiver buffers per receiving grid
+    const int32_t *recv_list;  // global receiver ids of this launch
+    const int32_t *recv_grid;  // per global receiver: receiving grid
+    const int32_t *recv_row;   // per global receiver: row in its grid's buffer
+    const int8_t *ent_grid;    // per (receiver, entry): donor grid
+    const int32_t *ent_pt;     // per (receiver, entry): donor point
+    const double *ent_w;       // per (receiver, entry): weight
+    int64_t nrecv;
+    int S;                     // entries per receiver (power of two, <= 64)
+    int dim, nv, sbp;
+    Phys ph;
+};
+
+// ---------------------------------------------------------------- launches
+hipError_t launch_grad(const GridDev &g, int sbp, double gm1, const double *q, double *grad, hipStream_t st);
+hipError_t launch_rhs(const GridDev &g, const GridDev *g_dev, int sbp, const Phys &ph, const double *q,
+                      const double *grad, double *F, const Combine &cb, hipStream_t st);
+hipError_t launch_donor(const DonorLaunch &a, hipStream_t st);
+hipError_t launch_combine(int64_t n, const double *y, const Combine &cb, hipStream_t st);
+hipError_t launch_axpy(int64_t n, const double *y, double a, const double *x, double *out, hipStream_t st);
+hipError_t launch_rk3_final(int64_t n, const double *y, double a, const double *k1, const double *k3,
+                            double *out, hipStream_t st);
+hipError_t launch_rk4_final(int64_t n, const double *y, double a, const double *k1, const double *k2,
+                            const double *k3, const double *k4, double *out, hipStream_t st);
+hipError_t launch_metrics2d(const GridDev &g, int sbp, const double *x, const double *y,
+                            const double per[2][2], double *metric, hipStream_t st);
+hipError_t launch_dt(const GridDev &g, const Phys &ph, const double *q, double *dt, hipStream_t st);
+// block-partial reductions: mode 0 = min, 1 = max |x| (NaN/Inf -> +inf)
+hipError_t launch_reduce(int64_t n, const double *x, int mode, double *partial, int nblocks, hipStream_t st);
+
+}  // namespace mrk

@@ -1,0 +1,753 @@
+// gfx950 kernels of the SBP-SAT overset right-hand side and the AB/MRAB
+// history combination.  FP64 throughout; the stencils are bandwidth bound and
+// use no matrix cores.
+//
+// Paper: Mikida, Kloeckner, Bodony, "Multi-Rate Time Integration on Overset
+// Meshes" -- governing equations and viscous stress (Appendix "Spatial
+// Accuracy of Right-Hand Sides"), second derivatives as two applications of
+// the first-derivative SBP operator (same Appendix), SAT interface penalty
+// eq. (int), AB combination eq. (ab_general), timestep eq. (ts_inv)-(ts_overall).
+#include "kern.h"
+
+#include <math.h>
+
+namespace mrk {
+
+template <int K>
+struct Vec {
+    double v[K];
+};
+
+// -------------------------------------------------------------- SBP rows
+// Diagonal-norm SBP 4-2 closure rows (left end); the right end mirrors them
+// with negated signs.  Interior: (1/12, -2/3, 0, 2/3, -1/12).
+// SBP 2-1: closure (-1, 1); interior (-1/2, 0, 1/2).
+#define C42_00 (-24.0 / 17.0)
+#define C42_01 (59.0 / 34.0)
+#define C42_02 (-4.0 / 17.0)
+#define C42_03 (-3.0 / 34.0)
+#define C42_20 (4.0 / 43.0)
+#define C42_21 (-59.0 / 86.0)
+#define C42_23 (59.0 / 86.0)
+#define C42_24 (-4.0 / 43.0)
+#define C42_30 (3.0 / 98.0)
+#define C42_32 (-59.0 / 98.0)
+#define C42_34 (32.0 / 49.0)
+#define C42_35 (-4.0 / 49.0)
+
+// First derivative (index spacing 1) of a K-vector field at a point whose
+// class row is `row`; f(o) returns the field at line offset o.
+template <int SBP, int K, class F>
+__device__ __forceinline__ Vec<K> dsbp(int row, F &&f)
+{
+    Vec<K> r;
+#pragma unroll
+    for (int k = 0; k < K; ++k) r.v[k] = 0.0;
+    auto add = [&](double c, int o) {
+        Vec<K> x = f(o);
+#pragma unroll
+        for (int k = 0; k < K; ++k) r.v[k] += c * x.v[k];
+    };
+    if (row == 0) {
+        if constexpr (SBP == 21) {
+            add(-0.5, -1); add(0.5, 1);
+        } else {
+            add(1.0 / 12.0, -2); add(-2.0 / 3.0, -1); add(2.0 / 3.0, 1); add(-1.0 / 12.0, 2);
+        }
+    } else if constexpr (SBP == 21) {
+        if (row == 1) { add(-1.0, 0); add(1.0, 1); }
+        else          { add(1.0, 0); add(-1.0, -1); }
+    } else {
+        switch (row) {
+        case 1: add(C42_00, 0); add(C42_01, 1); add(C42_02, 2); add(C42_03, 3); break;
+        case 2: add(-0.5, -1); add(0.5, 1); break;
+        case 3: add(C42_20, -2); add(C42_21, -1); add(C42_23, 1); add(C42_24, 2); break;
+        case 4: add(C42_30, -3); add(C42_32, -1); add(C42_34, 1); add(C42_35, 2); break;
+        case 5: add(-C42_00, 0); add(-C42_01, -1); add(-C42_02, -2); add(-C42_03, -3); break;
+        case 6: add(0.5, 1); add(-0.5, -1); break;
+        case 7: add(-C42_20, 2); add(-C42_21, 1); add(-C42_23, -1); add(-C42_24, -2); break;
+        default: add(-C42_30, 3); add(-C42_32, 1); add(-C42_34, -1); add(-C42_35, -2); break;
+        }
+    }
+    return r;
+}
+
+// neighbour along direction d at line offset o (periodic wrap)
+__device__ __forceinline__ int64_t nbr(const GridDev &g, int64_t p, const int *ic, int d, int o)
+{
+    int j = ic[d] + o;
+    if (g.periodic[d]) j = j < 0 ? j + g.n[d] : (j >= g.n[d] ? j - g.n[d] : j);
+    return p + (int64_t)(j - ic[d]) * g.stride[d];
+}
+
+__device__ __forceinline__ void coords(const GridDev &g, int64_t p, int *ic)
+{
+    ic[0] = (int)(p % g.n[0]);
+    int64_t r = p / g.n[0];
+    ic[1] = (int)(r % g.n[1]);
+    ic[2] = (int)(r / g.n[1]);
+}
+
+// primitives (u_1..u_D, T) of a conserved state
+template <int DIM>
+__device__ __forceinline__ Vec<DIM + 1> prim(const double *q, double gm1)
+{
+    Vec<DIM + 1> r;
+    double ri = 1.0 / q[0];
+    double ke = 0.0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        r.v[i] = q[1 + i] * ri;
+        ke += r.v[i] * q[1 + i];
+    }
+    double p = gm1 * (q[DIM + 1] - 0.5 * ke);
+    r.v[DIM] = p * ri;
+    return r;
+}
+
+template <int DIM>
+__device__ __forceinline__ void load_q(const double *q, int64_t N, int64_t p, double *out)
+{
+#pragma unroll
+    for (int v = 0; v < DIM + 2; ++v) out[v] = q[v * N + p];
+}
+
+// gradient d(phi_a)/dx_j of (u_1..u_D, T) at point p; qload(idx, out[nv])
+template <int DIM, int SBP, int CART, class QL>
+__device__ __forceinline__ void gradient(const GridDev &g, int64_t p, const int *ic, double gm1, QL &&qload,
+                                         double gr[DIM + 1][DIM])
+{
+    Vec<DIM + 1> dxi[DIM];
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) {
+        int row = g.cls[m * g.npts + p] & 15;
+        dxi[m] = dsbp<SBP, DIM + 1>(row, [&](int o) {
+            double qq[DIM + 2];
+            qload(nbr(g, p, ic, m, o), qq);
+            return prim<DIM>(qq, gm1);
+        });
+    }
+    if constexpr (CART) {
+#pragma unroll
+        for (int a = 0; a <= DIM; ++a)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) gr[a][j] = g.inv_h[j] * dxi[j].v[a];
+    } else {
+        const int64_t N = g.npts;
+        double J = g.metric[(int64_t)(DIM * DIM) * N + p];
+        double M[DIM][DIM];
+#pragma unroll
+        for (int m = 0; m < DIM; ++m)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) M[m][j] = g.metric[(int64_t)(m * DIM + j) * N + p];
+#pragma unroll
+        for (int a = 0; a <= DIM; ++a)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) {
+                double s = 0.0;
+#pragma unroll
+                for (int m = 0; m < DIM; ++m) s += M[m][j] * dxi[m].v[a];
+                gr[a][j] = J * s;
+            }
+    }
+}
+
+// Cartesian viscous flux vectors (components 1..nv-1) at a point
+template <int DIM>
+__device__ __forceinline__ void viscous_flux(const Phys &ph, const double *u, double gr[DIM + 1][DIM],
+                                             double Fv[DIM][DIM + 1])
+{
+    double mre = ph.mu / ph.Re, lre = ph.lam / ph.Re;
+    double kc = ph.mu * ph.gamma / ((ph.gamma - 1.0) * ph.Re * ph.Pr);
+    double div = 0.0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) div += gr[i][i];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+        double w = 0.0;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) {
+            double tau = mre * (gr[i][j] + gr[j][i]);
+            if (i == j) tau += lre * div;
+            Fv[j][i] = tau;
+            w += u[i] * tau;
+        }
+        Fv[j][DIM] = w + kc * gr[DIM][j];
+    }
+}
+
+// ------------------------------------------------------------ gradient pass
+template <int DIM, int SBP, int CART>
+__global__ void __launch_bounds__(256) k_grad(GridDev g, double gm1, const double *__restrict__ q,
+                                              double *__restrict__ grad)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= g.npts) return;
+    const int64_t N = g.npts;
+    if ((g.cls[p] & 15) == CLS_HOLE) {
+#pragma unroll
+        for (int k = 0; k < DIM * (DIM + 1); ++k) grad[k * N + p] = 0.0;
+        return;
+    }
+    int ic[3];
+    coords(g, p, ic);
+    double gr[DIM + 1][DIM];
+    gradient<DIM, SBP, CART>(g, p, ic, gm1, [&](int64_t idx, double *o) { load_q<DIM>(q, N, idx, o); }, gr);
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) grad[(int64_t)(a * DIM + j) * N + p] = gr[a][j];
+}
+
+// --------------------------------------------------------- SAT (closed form)
+// K^{+-} dQ for the Euler flux Jacobian along the (non-normalised) direction
+// n, at state q, via characteristic wave strengths (entropy + shear waves at
+// U, acoustic waves at U +- c|n|); sgn = +1 for K+, -1 for K-.
+template <int DIM>
+__device__ __forceinline__ void k_apply(double gamma, const double *q, const double *n, int sgn, const double *dQ,
+                                        double *out)
+{
+    double rho = q[0], ri = 1.0 / rho;
+    double u[DIM], ke = 0.0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) { u[i] = q[1 + i] * ri; ke += u[i] * u[i]; }
+    double p = (gamma - 1.0) * (q[DIM + 1] - 0.5 * rho * ke);
+    double c2 = gamma * p * ri, c = sqrt(c2);
+    double H = (q[DIM + 1] + p) * ri;
+    double L2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) L2 += n[j] * n[j];
+    double L = sqrt(L2), Li = 1.0 / L;
+    double nh[DIM], un = 0.0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) { nh[j] = n[j] * Li; un += u[j] * nh[j]; }
+    double U = un * L;
+    // linearised primitive differences
+    double drho = dQ[0];
+    double du[DIM], udm = 0.0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) { du[i] = (dQ[1 + i] - u[i] * drho) * ri; udm += u[i] * dQ[1 + i]; }
+    double dp = (gamma - 1.0) * (dQ[DIM + 1] - udm + 0.5 * ke * drho);
+    double dun = 0.0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) dun += du[i] * nh[i];
+    double ae = drho - dp / c2;
+    double ap = (dp + rho * c * dun) / (2.0 * c2);
+    double am = (dp - rho * c * dun) / (2.0 * c2);
+    double l0 = U, lp = U + c * L, lm = U - c * L;
+    double w0 = 0.5 * (fabs(l0) + sgn * l0);
+    double wp = 0.5 * (fabs(lp) + sgn * lp);
+    double wm = 0.5 * (fabs(lm) + sgn * lm);
+    double a0 = w0 * ae, bp = wp * ap, bm = wm * am;
+    out[0] = a0 + bp + bm;
+    double us = 0.0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        double s = rho * (du[i] - dun * nh[i]);
+        us += u[i] * s;
+        out[1 + i] = a0 * u[i] + w0 * s + bp * (u[i] + c * nh[i]) + bm * (u[i] - c * nh[i]);
+    }
+    out[DIM + 1] = a0 * 0.5 * ke + w0 * us + bp * (H + c * un) + bm * (H - c * un);
+}
+
+__device__ __forceinline__ double add_nc(double acc, double c, double f)
+{
+#pragma clang fp contract(off)
+    double t = c * f;
+    return acc + t;
+}
+
+// --------------------------------------------- fused flux divergence + SAT + AB
+template <int DIM, int SBP, int CART>
+__global__ void __launch_bounds__(256) k_rhs(GridDev g, Phys ph, const double *__restrict__ q,
+                                             const double *__restrict__ grad, double *__restrict__ F,
+                                             Combine cb)
+{
+    constexpr int NV = DIM + 2;
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= g.npts) return;
+    const int64_t N = g.npts;
+    const double gm1 = ph.gamma - 1.0;
+    int c0 = g.cls[p] & 15;
+    double r[NV];
+    if (c0 == CLS_HOLE) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) r[v] = 0.0;
+    } else {
+        int ic[3];
+        coords(g, p, ic);
+        // contravariant flux of direction m at point idx
+        auto fhat = [&](int m, int64_t idx) {
+            double qq[NV];
+            load_q<DIM>(q, N, idx, qq);
+            double ri = 1.0 / qq[0];
+            double u[DIM], ke = 0.0;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) { u[i] = qq[1 + i] * ri; ke += u[i] * qq[1 + i]; }
+            double pr = gm1 * (qq[DIM + 1] - 0.5 * ke);
+            double gr[DIM + 1][DIM];
+#pragma unroll
+            for (int a = 0; a <= DIM; ++a)
+#pragma unroll
+                for (int j = 0; j < DIM; ++j) gr[a][j] = grad[(int64_t)(a * DIM + j) * N + idx];
+            double Fv[DIM][DIM + 1];
+            viscous_flux<DIM>(ph, u, gr, Fv);
+            Vec<NV> out;
+            if constexpr (CART) {
+                out.v[0] = qq[1 + m];
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) out.v[1 + i] = qq[1 + i] * u[m] + (i == m ? pr : 0.0) - Fv[m][i];
+                out.v[NV - 1] = (qq[NV - 1] + pr) * u[m] - Fv[m][DIM];
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) out.v[v] = 0.0;
+#pragma unroll
+                for (int j = 0; j < DIM; ++j) {
+                    double Mmj = g.metric[(int64_t)(m * DIM + j) * N + idx];
+                    out.v[0] += Mmj * qq[1 + j];
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i)
+                        out.v[1 + i] += Mmj * (qq[1 + i] * u[j] + (i == j ? pr : 0.0) - Fv[j][i]);
+                    out.v[NV - 1] += Mmj * ((qq[NV - 1] + pr) * u[j] - Fv[j][DIM]);
+                }
+            }
+            return out;
+        };
+        double acc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+            int row = g.cls[m * N + p] & 15;
+            Vec<NV> d = dsbp<SBP, NV>(row, [&](int o) { return fhat(m, nbr(g, p, ic, m, o)); });
+            double sc = CART ? g.inv_h[m] : 1.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] += sc * d.v[v];
+        }
+        double J = CART ? 1.0 : g.metric[(int64_t)(DIM * DIM) * N + p];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) r[v] = -J * acc[v];
+
+        // SAT penalties at run ends (directions ascending, run start first)
+        bool any = false;
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+            int c = g.cls[m * N + p];
+            any |= ((c >> 4) & 3) != 0;
+        }
+        if (any) {
+            double qp[NV];
+            load_q<DIM>(q, N, p, qp);
+            double u[DIM];
+            double ri = 1.0 / qp[0];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) u[i] = qp[1 + i] * ri;
+            double gr[DIM + 1][DIM];
+#pragma unroll
+            for (int a = 0; a <= DIM; ++a)
+#pragma unroll
+                for (int j = 0; j < DIM; ++j) gr[a][j] = grad[(int64_t)(a * DIM + j) * N + p];
+            double Fv[DIM][DIM + 1];
+            viscous_flux<DIM>(ph, u, gr, Fv);
+            for (int m = 0; m < DIM; ++m) {
+                int c = g.cls[m * N + p];
+                int bc = (c >> 4) & 3;
+                if (!bc) continue;
+                int row = c & 15;
+                int sgn = (row == 1) ? 1 : -1;
+                double kap[DIM], k2 = 0.0;
+                if constexpr (CART) {
+#pragma unroll
+                    for (int j = 0; j < DIM; ++j) kap[j] = (j == m) ? g.inv_h[m] : 0.0;
+                } else {
+                    double Jp = g.metric[(int64_t)(DIM * DIM) * N + p];
+#pragma unroll
+                    for (int j = 0; j < DIM; ++j) kap[j] = Jp * g.metric[(int64_t)(m * DIM + j) * N + p];
+                }
+#pragma unroll
+                for (int j = 0; j < DIM; ++j) k2 += kap[j] * kap[j];
+                double dQ[NV], dV[NV], s2[NV];
+                double sigI, sig1 = ph.mu * k2 / (2.0 * ph.Re);
+                bool use_s2 = true;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) s2[v] = 0.0;
+                // own viscous flux along kappa (components 1..nv-1)
+#pragma unroll
+                for (int v = 1; v < NV; ++v) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int j = 0; j < DIM; ++j) s += kap[j] * Fv[j][v - 1];
+                    s2[v] = s;
+                }
+                if (bc == 1) {
+                    const double *rb = g.recv + (int64_t)g.recv_idx[p] * (NV + DIM * (NV - 1));
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) { dQ[v] = qp[v] - rb[v]; dV[v] = dQ[v]; }
+#pragma unroll
+                    for (int v = 1; v < NV; ++v) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int j = 0; j < DIM; ++j) s += kap[j] * rb[NV + j * (NV - 1) + (v - 1)];
+                        s2[v] -= s;
+                    }
+                    sigI = ph.sig_iface;
+                } else if (bc == 2) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) { dQ[v] = qp[v] - ph.q_inf[v]; dV[v] = dQ[v]; }
+                    sigI = ph.sig_bc;
+                } else {
+                    // wall: reflected normal momentum (inviscid), rest at T_wall (viscous)
+                    double kn = sqrt(k2), mn = 0.0;
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i) mn += qp[1 + i] * kap[i];
+                    mn /= kn;
+                    dQ[0] = 0.0;
+                    dV[0] = 0.0;
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i) { dQ[1 + i] = 2.0 * mn * kap[i] / kn; dV[1 + i] = qp[1 + i]; }
+                    dQ[NV - 1] = 0.0;
+                    dV[NV - 1] = qp[NV - 1] - qp[0] * ph.T_wall / (ph.gamma - 1.0);
+                    sigI = ph.sig_bc;
+                    sig1 = ph.wall_visc * ph.mu * k2 / ph.Re;
+                    use_s2 = false;
+                }
+                double KdQ[NV];
+                k_apply<DIM>(ph.gamma, qp, kap, sgn, dQ, KdQ);
+                double hs = 0.5 * sgn;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    double pen = -(sigI * KdQ[v] + sig1 * dV[v]) * ph.p0inv;
+                    if (use_s2) pen += hs * s2[v] * ph.p0inv;
+                    r[v] += pen;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v * N + p] = r[v];
+    if (cb.m > 0) {
+        // y_next = y + sum_j c_j F_j, oldest first, the new F last; each
+        // product and sum rounded separately
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            int64_t e = v * N + p;
+            double acc = q[e];
+            for (int j = 0; j < cb.m - 1; ++j) acc = add_nc(acc, cb.c[j], cb.hist[j][e]);
+            acc = add_nc(acc, cb.c[cb.m - 1], r[v]);
+            cb.y_next[e] = acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- donors
+// One lane per (receiver, stencil entry): donor state (extrapolated in time
+// when the donor grid is mid-step), donor viscous flux from the donor grid's
+// own SBP gradient, times the weight; a fixed butterfly over the S lanes of a
+// receiver sums the stencil.
+template <int DIM, int SBP>
+__global__ void __launch_bounds__(256) k_donor(DonorLaunch a)
+{
+    constexpr int NV = DIM + 2;
+    constexpr int RB = NV + DIM * (NV - 1);
+    int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t k = lane / a.S;
+    int e = (int)(lane % a.S);
+    if (k >= a.nrecv) return;                 // whole groups of S lanes leave together
+    int rid = a.recv_list[k];
+    int64_t ent = (int64_t)rid * a.S + e;
+    int dg = a.ent_grid[ent];
+    int64_t p = a.ent_pt[ent];
+    double w = a.ent_w[ent];
+    const GridDev &g = a.grids[dg];
+    const StateSrc &s = a.src[dg];
+    const int64_t N = g.npts;
+    auto qload = [&](int64_t idx, double *o) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            int64_t el = v * N + idx;
+            double acc = s.y[el];
+            if (s.mid)
+                for (int j = 0; j < s.m; ++j) acc = add_nc(acc, s.beta[j], s.hist[j][el]);
+            o[v] = acc;
+        }
+    };
+    double qp[NV];
+    qload(p, qp);
+    int ic[3];
+    coords(g, p, ic);
+    double gr[DIM + 1][DIM];
+    const double gm1 = a.ph.gamma - 1.0;
+    if (g.cartesian)
+        gradient<DIM, SBP, 1>(g, p, ic, gm1, qload, gr);
+    else
+        gradient<DIM, SBP, 0>(g, p, ic, gm1, qload, gr);
+    double val[RB];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) val[v] = w * qp[v];
+    {
+        double u[DIM];
+        double ri = 1.0 / qp[0];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) u[i] = qp[1 + i] * ri;
+        double Fv[DIM][DIM + 1];
+        viscous_flux<DIM>(a.ph, u, gr, Fv);
+#pragma unroll
+        for (int j = 0; j < DIM; ++j)
+#pragma unroll
+            for (int v = 1; v < NV; ++v) val[NV + j * (NV - 1) + (v - 1)] = w * Fv[j][v - 1];
+    }
+    for (int off = 1; off < a.S; off <<= 1) {
+#pragma unroll
+        for (int t = 0; t < RB; ++t) val[t] += __shfl_xor(val[t], off, 64);
+    }
+    if (e == 0) {
+        double *o = a.out[a.recv_grid[rid]] + (int64_t)a.recv_row[rid] * RB;
+#pragma unroll
+        for (int t = 0; t < RB; ++t) o[t] = val[t];
+    }
+}
+
+// ---------------------------------------------------------------- elementwise
+__global__ void k_combine(int64_t n, const double *__restrict__ y, Combine cb)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double acc = y[e];
+    for (int j = 0; j < cb.m; ++j) acc = add_nc(acc, cb.c[j], cb.hist[j][e]);
+    cb.y_next[e] = acc;
+}
+
+__global__ void k_axpy(int64_t n, const double *__restrict__ y, double a, const double *__restrict__ x,
+                       double *__restrict__ out)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) out[e] = y[e] + a * x[e];
+}
+
+__global__ void k_rk3_final(int64_t n, const double *__restrict__ y, double a, const double *__restrict__ k1,
+                            const double *__restrict__ k3, double *__restrict__ out)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) out[e] = y[e] + a * (k1[e] + 3.0 * k3[e]);
+}
+
+__global__ void k_rk4_final(int64_t n, const double *__restrict__ y, double a, const double *__restrict__ k1,
+                            const double *__restrict__ k2, const double *__restrict__ k3,
+                            const double *__restrict__ k4, double *__restrict__ out)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) out[e] = y[e] + a * (k1[e] + 2.0 * k2[e] + 2.0 * k3[e] + k4[e]);
+}
+
+// ---------------------------------------------------------------- setup
+// 2D metric terms by the grid's own full-line SBP derivative of the
+// coordinates (closures at non-periodic grid ends; coordinate jumps across
+// periodic seams)
+template <int SBP>
+__global__ void k_metrics2d(GridDev g, const double *__restrict__ x, const double *__restrict__ y, double px0,
+                            double px1, double py0, double py1, double *__restrict__ M)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= g.npts) return;
+    constexpr int NB = SBP == 21 ? 1 : 4;
+    int ic[3];
+    coords(g, p, ic);
+    double d[2][2];   // d[coord][dir]
+    const double perx[2] = {px0, px1}, pery[2] = {py0, py1};
+    for (int m = 0; m < 2; ++m) {
+        int n = g.n[m], i = ic[m];
+        int row = 0;
+        if (!g.periodic[m]) row = i < NB ? 1 + i : (i >= n - NB ? 5 + (n - 1 - i) : 0);
+        Vec<2> r = dsbp<SBP, 2>(row, [&](int o) {
+            int j = i + o;
+            double jx = 0.0, jy = 0.0;
+            if (g.periodic[m]) {
+                if (j < 0) { j += n; jx = -perx[m]; jy = -pery[m]; }
+                else if (j >= n) { j -= n; jx = perx[m]; jy = pery[m]; }
+            }
+            int64_t idx = p + (int64_t)(j - i) * g.stride[m];
+            Vec<2> v;
+            v.v[0] = x[idx] + jx;
+            v.v[1] = y[idx] + jy;
+            return v;
+        });
+        d[0][m] = r.v[0];
+        d[1][m] = r.v[1];
+    }
+    const int64_t N = g.npts;
+    double jinv = d[0][0] * d[1][1] - d[0][1] * d[1][0];
+    M[0 * N + p] = d[1][1];
+    M[1 * N + p] = -d[0][1];
+    M[2 * N + p] = -d[1][0];
+    M[3 * N + p] = d[0][0];
+    M[4 * N + p] = 1.0 / jinv;
+}
+
+template <int DIM>
+__global__ void k_dt(GridDev g, Phys ph, const double *__restrict__ q, double *__restrict__ dt)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= g.npts) return;
+    if ((g.cls[p] & 15) == CLS_HOLE) { dt[p] = INFINITY; return; }
+    const int64_t N = g.npts;
+    double qq[DIM + 2];
+    load_q<DIM>(q, N, p, qq);
+    double ri = 1.0 / qq[0], u[DIM], ke = 0.0;
+    for (int i = 0; i < DIM; ++i) { u[i] = qq[1 + i] * ri; ke += u[i] * qq[1 + i]; }
+    double pr = (ph.gamma - 1.0) * (qq[DIM + 1] - 0.5 * ke);
+    double c = sqrt(ph.gamma * pr * ri);
+    double J, adv = 0.0, sn = 0.0;
+    if (g.cartesian) {
+        double vol = 1.0;
+        for (int m = 0; m < DIM; ++m) vol /= g.inv_h[m];
+        J = 1.0 / vol;
+        for (int m = 0; m < DIM; ++m) {
+            double Mm = vol * g.inv_h[m];
+            adv += fabs(u[m] * Mm);
+            sn += Mm;
+        }
+    } else {
+        J = g.metric[(int64_t)(DIM * DIM) * N + p];
+        for (int m = 0; m < DIM; ++m) {
+            double dot = 0.0, nrm = 0.0;
+            for (int j = 0; j < DIM; ++j) {
+                double Mmj = g.metric[(int64_t)(m * DIM + j) * N + p];
+                dot += u[j] * Mmj;
+                nrm += Mmj * Mmj;
+            }
+            adv += fabs(dot);
+            sn += sqrt(nrm);
+        }
+    }
+    double nu = fmax(ph.mu, ph.gamma * ph.mu / ph.Pr) * ri / ph.Re;
+    dt[p] = fabs(1.0 / J) / (adv + c * sn + 2.0 * nu * fabs(J) * sn * sn);
+}
+
+__global__ void __launch_bounds__(256) k_reduce(int64_t n, const double *__restrict__ x, int mode,
+                                                double *__restrict__ partial)
+{
+    __shared__ double sh[256];
+    double acc = mode == 0 ? INFINITY : 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        double v = x[e];
+        if (mode == 0) acc = fmin(acc, v);
+        else acc = isfinite(v) ? fmax(acc, fabs(v)) : INFINITY;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            double o = sh[threadIdx.x + s];
+            sh[threadIdx.x] = mode == 0 ? fmin(sh[threadIdx.x], o) : fmax(sh[threadIdx.x], o);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// ---------------------------------------------------------------- launchers
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+#define DISPATCH_RHS(DIM, SBP, CART)                                                                  \
+    hipLaunchKernelGGL((k_rhs<DIM, SBP, CART>), dim3(nblk(g.npts, 256)), dim3(256), 0, st, g, ph, q, \
+                       grad, F, cb)
+
+hipError_t launch_rhs(const GridDev &g, const GridDev *, int sbp, const Phys &ph, const double *q,
+                      const double *grad, double *F, const Combine &cb, hipStream_t st)
+{
+    if (g.dim == 2 && sbp == 21 && g.cartesian) DISPATCH_RHS(2, 21, 1);
+    else if (g.dim == 2 && sbp == 21) DISPATCH_RHS(2, 21, 0);
+    else if (g.dim == 2 && sbp == 42 && g.cartesian) DISPATCH_RHS(2, 42, 1);
+    else if (g.dim == 2 && sbp == 42) DISPATCH_RHS(2, 42, 0);
+    else if (g.dim == 3 && sbp == 21 && g.cartesian) DISPATCH_RHS(3, 21, 1);
+    else if (g.dim == 3 && sbp == 42 && g.cartesian) DISPATCH_RHS(3, 42, 1);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+#define DISPATCH_GRAD(DIM, SBP, CART) \
+    hipLaunchKernelGGL((k_grad<DIM, SBP, CART>), dim3(nblk(g.npts, 256)), dim3(256), 0, st, g, gm1, q, grad)
+
+hipError_t launch_grad(const GridDev &g, int sbp, double gm1, const double *q, double *grad, hipStream_t st)
+{
+    if (g.dim == 2 && sbp == 21 && g.cartesian) DISPATCH_GRAD(2, 21, 1);
+    else if (g.dim == 2 && sbp == 21) DISPATCH_GRAD(2, 21, 0);
+    else if (g.dim == 2 && sbp == 42 && g.cartesian) DISPATCH_GRAD(2, 42, 1);
+    else if (g.dim == 2 && sbp == 42) DISPATCH_GRAD(2, 42, 0);
+    else if (g.dim == 3 && sbp == 21 && g.cartesian) DISPATCH_GRAD(3, 21, 1);
+    else if (g.dim == 3 && sbp == 42 && g.cartesian) DISPATCH_GRAD(3, 42, 1);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_donor(const DonorLaunch &a, hipStream_t st)
+{
+    if (a.nrecv == 0) return hipSuccess;
+    int64_t lanes = a.nrecv * a.S;
+    if (a.dim == 2 && a.sbp == 21)
+        hipLaunchKernelGGL((k_donor<2, 21>), dim3(nblk(lanes, 256)), dim3(256), 0, st, a);
+    else if (a.dim == 2 && a.sbp == 42)
+        hipLaunchKernelGGL((k_donor<2, 42>), dim3(nblk(lanes, 256)), dim3(256), 0, st, a);
+    else if (a.dim == 3 && a.sbp == 21)
+        hipLaunchKernelGGL((k_donor<3, 21>), dim3(nblk(lanes, 256)), dim3(256), 0, st, a);
+    else if (a.dim == 3 && a.sbp == 42)
+        hipLaunchKernelGGL((k_donor<3, 42>), dim3(nblk(lanes, 256)), dim3(256), 0, st, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(int64_t n, const double *y, const Combine &cb, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_combine, dim3(nblk(n, 256)), dim3(256), 0, st, n, y, cb);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(int64_t n, const double *y, double a, const double *x, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_axpy, dim3(nblk(n, 256)), dim3(256), 0, st, n, y, a, x, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk3_final(int64_t n, const double *y, double a, const double *k1, const double *k3,
+                            double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rk3_final, dim3(nblk(n, 256)), dim3(256), 0, st, n, y, a, k1, k3, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk4_final(int64_t n, const double *y, double a, const double *k1, const double *k2,
+                            const double *k3, const double *k4, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rk4_final, dim3(nblk(n, 256)), dim3(256), 0, st, n, y, a, k1, k2, k3, k4, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_metrics2d(const GridDev &g, int sbp, const double *x, const double *y, const double per[2][2],
+                            double *metric, hipStream_t st)
+{
+    if (sbp == 21)
+        hipLaunchKernelGGL((k_metrics2d<21>), dim3(nblk(g.npts, 256)), dim3(256), 0, st, g, x, y, per[0][0],
+                           per[1][0], per[0][1], per[1][1], metric);
+    else
+        hipLaunchKernelGGL((k_metrics2d<42>), dim3(nblk(g.npts, 256)), dim3(256), 0, st, g, x, y, per[0][0],
+                           per[1][0], per[0][1], per[1][1], metric);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt(const GridDev &g, const Phys &ph, const double *q, double *dt, hipStream_t st)
+{
+    if (g.dim == 2)
+        hipLaunchKernelGGL((k_dt<2>), dim3(nblk(g.npts, 256)), dim3(256), 0, st, g, ph, q, dt);
+    else
+        hipLaunchKernelGGL((k_dt<3>), dim3(nblk(g.npts, 256)), dim3(256), 0, st, g, ph, q, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(int64_t n, const double *x, int mode, double *partial, int nblocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(nblocks), dim3(256), 0, st, n, x, mode, partial);
+    return hipGetLastError();
+}
+
+}  // namespace mrk

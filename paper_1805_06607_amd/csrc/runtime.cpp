@@ -1,0 +1,876 @@
+// Host runtime behind the C ABI of libmrab.so (include/mrab.h): run
+// classification of every grid line, donor tables, workspace layout, the
+// static multi-rate schedule and the RK bootstrap.  All device work is
+// enqueued on the context's stream.
+#include "../../include/mrab.h"
+#include "kern.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using mrk::GridDev;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+struct GridHost {
+    int dim = 2, kind = 0, rate = 1;
+    int n[3] = {1, 1, 1};
+    int periodic[3] = {0, 0, 0};
+    int64_t stride[3] = {1, 1, 1};
+    int64_t npts = 0;
+    double origin[3] = {0, 0, 0}, spacing[3] = {1, 1, 1};
+    double coord_period[3][3] = {{0}};
+    int face_bc[6] = {0};
+    std::vector<double> coords;
+    std::vector<int8_t> iblank;
+    std::vector<int8_t> cls;          // dim x npts
+    std::vector<int32_t> recv_idx;    // npts
+    std::vector<int64_t> recv_pts;    // registered receivers, row order
+    int64_t n_iface = 0;              // points ending a run on an interface face
+    // device
+    double *y[2] = {nullptr, nullptr};
+    int cur = 0;
+    double *hist = nullptr;
+    double *metric = nullptr, *coords_d = nullptr, *grad = nullptr, *recv_buf = nullptr, *dt = nullptr;
+    double *rk[5] = {nullptr};
+    int8_t *cls_d = nullptr;
+    int32_t *recv_idx_d = nullptr;
+    int32_t *recv_list_d = nullptr;   // global receiver ids of this grid
+    GridDev dev{};
+    int head = 0;
+};
+
+}  // namespace
+
+struct mr_ctx {
+    mr_params P{};
+    hipStream_t st = nullptr;
+    std::string err;
+    std::vector<GridHost> G;
+    int S = 0;
+    std::vector<int32_t> rgrid, rrow;
+    std::vector<int8_t> egrid;
+    std::vector<int32_t> ept;
+    std::vector<double> ew;
+    bool finalized = false, bound = false, have_dt = false, started = false;
+    size_t ws_bytes = 0;
+    char *ws = nullptr;
+    int rmax = 1;
+    double H = 0, h = 0, t = 0;
+    int64_t nmacro = 0;
+    std::vector<std::vector<long double>> alpha_own;                 // per grid
+    std::vector<std::vector<std::vector<long double>>> alpha_mid;   // per grid, per jp
+    std::vector<std::vector<double>> c_own;
+    std::vector<std::vector<std::vector<double>>> beta;
+    std::vector<std::vector<int32_t>> pat;                           // per k = 1..rmax
+    std::vector<int32_t> all_recv;
+    int32_t *pat_d[64] = {nullptr};
+    int32_t *all_recv_d = nullptr;
+    int32_t *rgrid_d = nullptr, *rrow_d = nullptr, *ept_d = nullptr;
+    int8_t *egrid_d = nullptr;
+    double *ew_d = nullptr;
+    GridDev *grids_d = nullptr;
+    double *partial = nullptr;
+    mrk::Phys ph{};
+    // per-launch timing
+    int tgrid = -1, tmax = 0, tcount = 0;
+    std::vector<hipEvent_t> ev;
+};
+
+namespace {
+
+int fail(mr_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(c, expr)                                                                     \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) return fail(c, MR_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int nclosure(int sbp) { return sbp == 21 ? 1 : 4; }
+
+// ------------------------------------------------------- AB coefficients
+// alpha (oldest first) for nodes -(m-1)..0 and target offset tau: Vandermonde
+// transpose system for m == n, minimum-norm solution for m > n.
+bool solve_ld(std::vector<std::vector<long double>> A, std::vector<long double> b, std::vector<long double> &x)
+{
+    int n = (int)A.size();
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+        if (A[piv][c] == 0.0L) return false;
+        std::swap(A[c], A[piv]);
+        std::swap(b[c], b[piv]);
+        for (int r = c + 1; r < n; ++r) {
+            long double f = A[r][c] / A[c][c];
+            for (int k = c; k < n; ++k) A[r][k] -= f * A[c][k];
+            b[r] -= f * b[c];
+        }
+    }
+    x.assign(n, 0.0L);
+    for (int r = n - 1; r >= 0; --r) {
+        long double s = b[r];
+        for (int k = r + 1; k < n; ++k) s -= A[r][k] * x[k];
+        x[r] = s / A[r][r];
+    }
+    return true;
+}
+
+bool ab_alpha(int n, int m, long double tau, std::vector<long double> &alpha)
+{
+    if (n < 1 || m < n || m > mrk::MAXH) return false;
+    std::vector<long double> t(m);
+    for (int j = 0; j < m; ++j) t[j] = -(long double)(m - 1 - j);
+    std::vector<std::vector<long double>> V(m, std::vector<long double>(n));
+    for (int j = 0; j < m; ++j) {
+        long double v = 1.0L;
+        for (int i = 0; i < n; ++i) { V[j][i] = v; v *= t[j]; }
+    }
+    std::vector<long double> b(n);
+    long double tp = tau;
+    for (int i = 0; i < n; ++i) { b[i] = tp / (long double)(i + 1); tp *= tau; }
+    if (m == n) {
+        std::vector<std::vector<long double>> VT(n, std::vector<long double>(n));
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) VT[i][j] = V[j][i];
+        return solve_ld(VT, b, alpha);
+    }
+    std::vector<std::vector<long double>> N(n, std::vector<long double>(n, 0.0L));
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k)
+            for (int j = 0; j < m; ++j) N[i][k] += V[j][i] * V[j][k];
+    std::vector<long double> z;
+    if (!solve_ld(N, b, z)) return false;
+    alpha.assign(m, 0.0L);
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < n; ++i) alpha[j] += V[j][i] * z[i];
+    return true;
+}
+
+// -------------------------------------------------------- run classification
+int classify(mr_ctx *c, GridHost &g)
+{
+    int nb = nclosure(c->P.sbp);
+    int64_t N = g.npts;
+    g.cls.assign((size_t)g.dim * N, 0);
+    for (int d = 0; d < g.dim; ++d) {
+        int nd = g.n[d];
+        int o1 = (d + 1) % g.dim, o2 = (d + 2) % g.dim;
+        int n1 = g.dim > 1 ? g.n[o1] : 1;
+        int n2 = g.dim > 2 ? g.n[o2] : 1;
+        std::vector<int64_t> idx(nd);
+        std::vector<char> a(nd);
+        for (int i2 = 0; i2 < n2; ++i2)
+            for (int i1 = 0; i1 < n1; ++i1) {
+                int64_t base = (int64_t)i1 * g.stride[o1] + (g.dim > 2 ? (int64_t)i2 * g.stride[o2] : 0);
+                bool all = true, none = true;
+                for (int i = 0; i < nd; ++i) {
+                    idx[i] = base + (int64_t)i * g.stride[d];
+                    a[i] = g.iblank[idx[i]] != 0;
+                    all = all && a[i];
+                    none = none && !a[i];
+                }
+                int8_t *cl = g.cls.data() + (size_t)d * N;
+                for (int i = 0; i < nd; ++i)
+                    if (!a[i]) cl[idx[i]] = mrk::CLS_HOLE;
+                if (none) continue;
+                if (all && g.periodic[d]) continue;   // endless periodic line: interior everywhere
+                // runs (start, length); periodic lines start scanning after a hole
+                int first = 0;
+                if (g.periodic[d]) {
+                    int h = 0;
+                    while (a[h]) ++h;
+                    first = h + 1;
+                }
+                int i = 0;
+                while (i < nd) {
+                    int k = (first + i) % nd;
+                    if (!a[k]) { ++i; continue; }
+                    int s = k, L = 0;
+                    while (i < nd && a[(first + i) % nd]) { ++L; ++i; }
+                    if (L < 2 * nb)
+                        return fail(c, MR_ERR_SETUP,
+                                    "run of %d points along direction %d shorter than two closures (%d)", L, d,
+                                    2 * nb);
+                    int e = (s + L - 1) % nd;
+                    int lo = (!g.periodic[d] && s == 0) ? g.face_bc[2 * d] : MR_BC_INTERFACE;
+                    int hi = (!g.periodic[d] && e == nd - 1) ? g.face_bc[2 * d + 1] : MR_BC_INTERFACE;
+                    if (lo == MR_BC_PERIODIC || hi == MR_BC_PERIODIC)
+                        return fail(c, MR_ERR_SETUP, "periodic flag on a non-periodic face (direction %d)", d);
+                    for (int r = 0; r < L; ++r) {
+                        int code = r < nb ? 1 + r : (r >= L - nb ? 5 + (L - 1 - r) : 0);
+                        if (r == 0) code |= lo << 4;
+                        if (r == L - 1) code |= hi << 4;
+                        cl[idx[(s + r) % nd]] = (int8_t)code;
+                    }
+                }
+            }
+    }
+    g.recv_idx.assign(N, -1);
+    g.n_iface = 0;
+    for (int64_t p = 0; p < N; ++p) {
+        bool iface = false;
+        for (int d = 0; d < g.dim; ++d) iface = iface || ((g.cls[(size_t)d * N + p] >> 4) & 3) == MR_BC_INTERFACE;
+        g.n_iface += iface;
+    }
+    return MR_OK;
+}
+
+bool is_iface(const GridHost &g, int64_t p)
+{
+    for (int d = 0; d < g.dim; ++d)
+        if (((g.cls[(size_t)d * g.npts + p] >> 4) & 3) == MR_BC_INTERFACE) return true;
+    return false;
+}
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count)
+    {
+        off = (off + ALIGN - 1) / ALIGN * ALIGN;
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+// lay out (base == nullptr: only measure) the workspace
+size_t layout(mr_ctx *c, char *base)
+{
+    Carver cv{base};
+    int m = c->P.hist_len;
+    for (auto &g : c->G) {
+        int nv = g.dim + 2;
+        int64_t N = g.npts;
+        g.y[0] = cv.take<double>((size_t)nv * N);
+        g.y[1] = cv.take<double>((size_t)nv * N);
+        g.hist = cv.take<double>((size_t)m * nv * N);
+        g.grad = cv.take<double>((size_t)g.dim * (g.dim + 1) * N);
+        for (int k = 0; k < 5; ++k) g.rk[k] = cv.take<double>((size_t)nv * N);
+        g.dt = cv.take<double>((size_t)N);
+        g.cls_d = cv.take<int8_t>((size_t)g.dim * N);
+        g.metric = g.kind == MR_CURVILINEAR ? cv.take<double>((size_t)(g.dim * g.dim + 1) * N) : nullptr;
+        g.coords_d = g.kind == MR_CURVILINEAR ? cv.take<double>((size_t)g.dim * N) : nullptr;
+        size_t nr = g.recv_pts.size();
+        g.recv_idx_d = nr ? cv.take<int32_t>((size_t)N) : nullptr;
+        g.recv_buf = nr ? cv.take<double>(nr * (nv + g.dim * (nv - 1))) : nullptr;
+        g.recv_list_d = nr ? cv.take<int32_t>(nr) : nullptr;
+    }
+    size_t R = c->rgrid.size();
+    c->rgrid_d = cv.take<int32_t>(R + 1);
+    c->rrow_d = cv.take<int32_t>(R + 1);
+    c->egrid_d = cv.take<int8_t>(R * c->S + 1);
+    c->ept_d = cv.take<int32_t>(R * c->S + 1);
+    c->ew_d = cv.take<double>(R * c->S + 1);
+    c->all_recv_d = cv.take<int32_t>(R + 1);
+    for (int k = 1; k <= c->rmax; ++k) c->pat_d[k] = cv.take<int32_t>(c->pat[k].size() + 1);
+    c->grids_d = cv.take<GridDev>(c->G.size());
+    c->partial = cv.take<double>(1024);
+    return cv.off + ALIGN;
+}
+
+double *slot(const mr_ctx *c, const GridHost &g, int j)   // j = 0 oldest .. m-1 newest
+{
+    int m = c->P.hist_len;
+    int s = ((g.head - (m - 1) + j) % m + m) % m;
+    return g.hist + (size_t)s * (g.dim + 2) * g.npts;
+}
+
+int donor_launch(mr_ctx *c, const int32_t *list_d, int64_t nrecv, const mrk::StateSrc *src, double *const *out)
+{
+    if (nrecv == 0) return MR_OK;
+    mrk::DonorLaunch a{};
+    a.grids = c->grids_d;
+    for (size_t g = 0; g < c->G.size(); ++g) {
+        a.src[g] = src[g];
+        a.out[g] = out[g];
+    }
+    a.recv_list = list_d;
+    a.recv_grid = c->rgrid_d;
+    a.recv_row = c->rrow_d;
+    a.ent_grid = c->egrid_d;
+    a.ent_pt = c->ept_d;
+    a.ent_w = c->ew_d;
+    a.nrecv = nrecv;
+    a.S = c->S;
+    a.dim = c->P.dim;
+    a.nv = c->P.dim + 2;
+    a.sbp = c->P.sbp;
+    a.ph = c->ph;
+    HIPCHK(c, mrk::launch_donor(a, c->st));
+    return MR_OK;
+}
+
+// right-hand side of one grid from state q into F (+ optional fused combine)
+int grid_rhs(mr_ctx *c, int gi, const double *q, double *F, const mrk::Combine &cb, bool timed)
+{
+    GridHost &g = c->G[gi];
+    HIPCHK(c, mrk::launch_grad(g.dev, c->P.sbp, c->P.gamma - 1.0, q, g.grad, c->st));
+    bool rec = timed && c->tgrid == gi && c->tcount < c->tmax;
+    if (rec) HIPCHK(c, hipEventRecord(c->ev[2 * c->tcount], c->st));
+    HIPCHK(c, mrk::launch_rhs(g.dev, c->grids_d + gi, c->P.sbp, c->ph, q, g.grad, F, cb, c->st));
+    if (rec) {
+        HIPCHK(c, hipEventRecord(c->ev[2 * c->tcount + 1], c->st));
+        c->tcount++;
+    }
+    return MR_OK;
+}
+
+// coupled right-hand side of all grids
+int rhs_all(mr_ctx *c, const double *const *q, double *const *F)
+{
+    mrk::StateSrc src[mrk::MAXG] = {};
+    double *out[mrk::MAXG] = {};
+    for (size_t g = 0; g < c->G.size(); ++g) {
+        src[g].y = q[g];
+        src[g].mid = 0;
+        out[g] = c->G[g].recv_buf;
+    }
+    int rc = donor_launch(c, c->all_recv_d, (int64_t)c->all_recv.size(), src, out);
+    if (rc) return rc;
+    mrk::Combine none{};
+    for (size_t g = 0; g < c->G.size(); ++g) {
+        rc = grid_rhs(c, (int)g, q[g], F[g], none, false);
+        if (rc) return rc;
+    }
+    return MR_OK;
+}
+
+int64_t nelem(const GridHost &g) { return (int64_t)(g.dim + 2) * g.npts; }
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+int mr_create(const mr_params *params, void *hip_stream, mr_ctx **out)
+{
+    if (!params || !out) return MR_ERR_ARG;
+    const mr_params &P = *params;
+    if ((P.dim != 2 && P.dim != 3) || (P.sbp != 21 && P.sbp != 42) || P.order < 1 || P.order > 4 ||
+        P.hist_len < P.order || P.hist_len > mrk::MAXH || !(P.gamma > 1.0) || !(P.Re > 0.0) || !(P.Pr > 0.0))
+        return MR_ERR_ARG;
+    mr_ctx *c = new mr_ctx();
+    c->P = P;
+    c->st = (hipStream_t)hip_stream;
+    c->ph.gamma = P.gamma;
+    c->ph.Re = P.Re;
+    c->ph.Pr = P.Pr;
+    c->ph.mu = P.mu;
+    c->ph.lam = P.lambda_over_mu * P.mu;
+    c->ph.sig_iface = P.sigma_I_iface;
+    c->ph.sig_bc = P.sigma_I_bc;
+    c->ph.T_wall = P.T_wall;
+    c->ph.wall_visc = P.wall_visc;
+    for (int v = 0; v < 5; ++v) c->ph.q_inf[v] = P.q_inf[v];
+    c->ph.p0inv = P.sbp == 21 ? 2.0 : 48.0 / 17.0;
+    *out = c;
+    return MR_OK;
+}
+
+int mr_add_grid(mr_ctx *c, const mr_grid_desc *d, int *grid_id)
+{
+    if (!c || !d) return MR_ERR_ARG;
+    if (c->finalized) return fail(c, MR_ERR_STATE, "mr_add_grid after mr_finalize");
+    if ((int)c->G.size() >= mrk::MAXG) return fail(c, MR_ERR_ARG, "at most %d grids", mrk::MAXG);
+    GridHost g;
+    g.dim = c->P.dim;
+    g.kind = d->kind;
+    g.rate = d->rate;
+    if (g.rate < 1) return fail(c, MR_ERR_SETUP, "rate must be >= 1");
+    if (g.kind == MR_CURVILINEAR && g.dim != 2)
+        return fail(c, MR_ERR_UNSUPPORTED, "curvilinear grids are supported in 2D only");
+    if (g.kind != MR_CARTESIAN && g.kind != MR_CURVILINEAR) return fail(c, MR_ERR_ARG, "bad grid kind");
+    g.npts = 1;
+    for (int k = 0; k < 3; ++k) {
+        g.n[k] = k < g.dim ? d->n[k] : 1;
+        g.periodic[k] = k < g.dim ? (d->periodic[k] != 0) : 0;
+        if (g.n[k] < 1) return fail(c, MR_ERR_ARG, "bad size");
+        g.stride[k] = g.npts;
+        g.npts *= g.n[k];
+        g.origin[k] = d->origin[k];
+        g.spacing[k] = d->spacing[k];
+        for (int j = 0; j < 3; ++j) g.coord_period[k][j] = d->coord_period[k][j];
+    }
+    if (g.npts >= ((int64_t)1 << 31)) return fail(c, MR_ERR_ARG, "grid too large for 32-bit point indices");
+    for (int k = 0; k < 2 * g.dim; ++k) {
+        g.face_bc[k] = d->face_bc[k];
+        if (g.face_bc[k] < 0 || g.face_bc[k] > 3) return fail(c, MR_ERR_ARG, "bad face flag");
+    }
+    if (g.kind == MR_CARTESIAN)
+        for (int k = 0; k < g.dim; ++k)
+            if (!(g.spacing[k] > 0)) return fail(c, MR_ERR_ARG, "bad spacing");
+    if (g.kind == MR_CURVILINEAR) {
+        if (!d->coords) return fail(c, MR_ERR_ARG, "curvilinear grid without coordinates");
+        g.coords.assign(d->coords, d->coords + (size_t)g.dim * g.npts);
+    }
+    g.iblank.assign(g.npts, 1);
+    if (d->iblank)
+        for (int64_t p = 0; p < g.npts; ++p) g.iblank[p] = d->iblank[p] ? 1 : 0;
+    int rc = classify(c, g);
+    if (rc) return rc;
+    c->G.push_back(std::move(g));
+    if (grid_id) *grid_id = (int)c->G.size() - 1;
+    return MR_OK;
+}
+
+int mr_set_overset(mr_ctx *c, int rg, int dg, int64_t n, int S, const int64_t *recv_pt, const int64_t *donor_pt,
+                   const double *w)
+{
+    if (!c) return MR_ERR_ARG;
+    if (c->finalized) return fail(c, MR_ERR_STATE, "mr_set_overset after mr_finalize");
+    if (rg < 0 || rg >= (int)c->G.size() || dg < 0 || dg >= (int)c->G.size() || rg == dg)
+        return fail(c, MR_ERR_ARG, "bad grid ids");
+    if (n < 0 || (n > 0 && (!recv_pt || !donor_pt || !w))) return fail(c, MR_ERR_ARG, "bad arrays");
+    if (S < 1 || S > 64 || (S & (S - 1))) return fail(c, MR_ERR_ARG, "stencil size must be a power of two <= 64");
+    if (c->S && c->S != S) return fail(c, MR_ERR_ARG, "stencil size differs from an earlier call");
+    c->S = S;
+    GridHost &R = c->G[rg];
+    GridHost &D = c->G[dg];
+    for (int64_t r = 0; r < n; ++r) {
+        int64_t p = recv_pt[r];
+        if (p < 0 || p >= R.npts) return fail(c, MR_ERR_ARG, "receiver index out of range");
+        if (!R.iblank[p] || !is_iface(R, p))
+            return fail(c, MR_ERR_SETUP, "point %lld of grid %d is not an interface run end", (long long)p, rg);
+        if (R.recv_idx[p] >= 0) return fail(c, MR_ERR_SETUP, "receiver %lld registered twice", (long long)p);
+        for (int e = 0; e < S; ++e) {
+            int64_t q = donor_pt[r * S + e];
+            if (q < 0 || q >= D.npts) return fail(c, MR_ERR_ARG, "donor index out of range");
+            if (!D.iblank[q]) return fail(c, MR_ERR_SETUP, "donor point %lld of grid %d is blanked", (long long)q, dg);
+        }
+        R.recv_idx[p] = (int32_t)R.recv_pts.size();
+        c->rgrid.push_back(rg);
+        c->rrow.push_back((int32_t)R.recv_pts.size());
+        R.recv_pts.push_back(p);
+        for (int e = 0; e < S; ++e) {
+            c->egrid.push_back((int8_t)dg);
+            c->ept.push_back((int32_t)donor_pt[r * S + e]);
+            c->ew.push_back(w[r * S + e]);
+        }
+    }
+    return MR_OK;
+}
+
+int mr_finalize(mr_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return MR_ERR_ARG;
+    if (c->finalized) return fail(c, MR_ERR_STATE, "mr_finalize called twice");
+    if (c->G.empty()) return fail(c, MR_ERR_STATE, "no grids");
+    for (size_t g = 0; g < c->G.size(); ++g)
+        if ((int64_t)c->G[g].recv_pts.size() != c->G[g].n_iface)
+            return fail(c, MR_ERR_SETUP, "grid %zu: %lld interface run ends but %zu receivers with donors", g,
+                        (long long)c->G[g].n_iface, c->G[g].recv_pts.size());
+    if (c->S == 0) c->S = 1;
+    c->rmax = 1;
+    for (auto &g : c->G) c->rmax = std::max(c->rmax, g.rate);
+    if (c->rmax > 63) return fail(c, MR_ERR_SETUP, "largest rate above 63");
+    for (auto &g : c->G)
+        if (c->rmax % g.rate) return fail(c, MR_ERR_SETUP, "rate %d does not divide %d", g.rate, c->rmax);
+    int n = c->P.order, m = c->P.hist_len;
+    c->alpha_own.assign(c->G.size(), {});
+    c->alpha_mid.assign(c->G.size(), {});
+    for (size_t g = 0; g < c->G.size(); ++g) {
+        if (!ab_alpha(n, m, 1.0L, c->alpha_own[g])) return fail(c, MR_ERR_SETUP, "AB coefficients");
+        int per = c->rmax / c->G[g].rate;
+        c->alpha_mid[g].assign(per, {});
+        for (int jp = 1; jp < per; ++jp)
+            if (!ab_alpha(n, m, (long double)jp / (long double)per, c->alpha_mid[g][jp]))
+                return fail(c, MR_ERR_SETUP, "AB coefficients");
+    }
+    c->pat.assign(c->rmax + 1, {});
+    c->all_recv.clear();
+    for (int32_t r = 0; r < (int32_t)c->rgrid.size(); ++r) c->all_recv.push_back(r);
+    for (int k = 1; k <= c->rmax; ++k)
+        for (int32_t r = 0; r < (int32_t)c->rgrid.size(); ++r) {
+            int per = c->rmax / c->G[c->rgrid[r]].rate;
+            if (k % per == 0) c->pat[k].push_back(r);
+        }
+    c->ws_bytes = layout(c, nullptr);
+    c->finalized = true;
+    *bytes = c->ws_bytes;
+    return MR_OK;
+}
+
+int mr_bind_workspace(mr_ctx *c, void *dev, size_t bytes)
+{
+    if (!c || !dev) return MR_ERR_ARG;
+    if (!c->finalized) return fail(c, MR_ERR_STATE, "mr_bind_workspace before mr_finalize");
+    if (c->bound) return fail(c, MR_ERR_STATE, "workspace already bound");
+    if (bytes < c->ws_bytes) return fail(c, MR_ERR_ARG, "workspace too small (%zu < %zu)", bytes, c->ws_bytes);
+    if ((uintptr_t)dev % ALIGN) return fail(c, MR_ERR_ARG, "workspace not 256-byte aligned");
+    c->ws = (char *)dev;
+    layout(c, c->ws);
+    HIPCHK(c, hipMemsetAsync(c->ws, 0, c->ws_bytes, c->st));
+    std::vector<GridDev> devs;
+    for (size_t gi = 0; gi < c->G.size(); ++gi) {
+        GridHost &g = c->G[gi];
+        HIPCHK(c, hipMemcpyAsync(g.cls_d, g.cls.data(), g.cls.size(), hipMemcpyHostToDevice, c->st));
+        if (!g.recv_pts.empty()) {
+            HIPCHK(c, hipMemcpyAsync(g.recv_idx_d, g.recv_idx.data(), g.recv_idx.size() * 4, hipMemcpyHostToDevice,
+                                     c->st));
+            std::vector<int32_t> lst;
+            for (int32_t r = 0; r < (int32_t)c->rgrid.size(); ++r)
+                if (c->rgrid[r] == (int32_t)gi) lst.push_back(r);
+            HIPCHK(c, hipMemcpyAsync(g.recv_list_d, lst.data(), lst.size() * 4, hipMemcpyHostToDevice, c->st));
+        }
+        GridDev &D = g.dev;
+        D.dim = g.dim;
+        D.nv = g.dim + 2;
+        for (int k = 0; k < 3; ++k) {
+            D.n[k] = g.n[k];
+            D.periodic[k] = g.periodic[k];
+            D.stride[k] = g.stride[k];
+            D.inv_h[k] = 1.0 / g.spacing[k];
+        }
+        D.npts = g.npts;
+        D.cartesian = g.kind == MR_CARTESIAN;
+        D.metric = g.metric;
+        D.cls = g.cls_d;
+        D.recv_idx = g.recv_idx_d;
+        D.recv = g.recv_buf;
+        if (g.kind == MR_CURVILINEAR) {
+            HIPCHK(c, hipMemcpyAsync(g.coords_d, g.coords.data(), g.coords.size() * 8, hipMemcpyHostToDevice, c->st));
+            double per[2][2] = {{g.coord_period[0][0], g.coord_period[0][1]}, {g.coord_period[1][0], g.coord_period[1][1]}};
+            HIPCHK(c, mrk::launch_metrics2d(D, c->P.sbp, g.coords_d, g.coords_d + g.npts, per, g.metric, c->st));
+        }
+        devs.push_back(D);
+    }
+    size_t R = c->rgrid.size();
+    if (R) {
+        HIPCHK(c, hipMemcpyAsync(c->rgrid_d, c->rgrid.data(), R * 4, hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, hipMemcpyAsync(c->rrow_d, c->rrow.data(), R * 4, hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, hipMemcpyAsync(c->egrid_d, c->egrid.data(), R * c->S, hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, hipMemcpyAsync(c->ept_d, c->ept.data(), R * c->S * 4, hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, hipMemcpyAsync(c->ew_d, c->ew.data(), R * c->S * 8, hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, hipMemcpyAsync(c->all_recv_d, c->all_recv.data(), R * 4, hipMemcpyHostToDevice, c->st));
+        for (int k = 1; k <= c->rmax; ++k)
+            if (!c->pat[k].empty())
+                HIPCHK(c, hipMemcpyAsync(c->pat_d[k], c->pat[k].data(), c->pat[k].size() * 4, hipMemcpyHostToDevice,
+                                         c->st));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->grids_d, devs.data(), devs.size() * sizeof(GridDev), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    c->bound = true;
+    return MR_OK;
+}
+
+int mr_set_state(mr_ctx *c, int g, const double *q)
+{
+    if (!c || !q || g < 0 || g >= (int)c->G.size()) return MR_ERR_ARG;
+    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_set_state before mr_bind_workspace");
+    GridHost &G = c->G[g];
+    HIPCHK(c, hipMemcpyAsync(G.y[G.cur], q, nelem(G) * 8, hipMemcpyDeviceToDevice, c->st));
+    c->started = false;
+    return MR_OK;
+}
+
+int mr_get_state(mr_ctx *c, int g, double *q)
+{
+    if (!c || !q || g < 0 || g >= (int)c->G.size()) return MR_ERR_ARG;
+    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_get_state before mr_bind_workspace");
+    GridHost &G = c->G[g];
+    HIPCHK(c, hipMemcpyAsync(q, G.y[G.cur], nelem(G) * 8, hipMemcpyDeviceToDevice, c->st));
+    return MR_OK;
+}
+
+int mr_rhs(mr_ctx *c, double, const double *const *q, double *const *F)
+{
+    if (!c || !q || !F) return MR_ERR_ARG;
+    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_rhs before mr_bind_workspace");
+    for (size_t g = 0; g < c->G.size(); ++g)
+        if (!q[g] || !F[g]) return fail(c, MR_ERR_ARG, "null state or output pointer");
+    return rhs_all(c, q, F);
+}
+
+int mr_num_receivers(const mr_ctx *c, int g, int64_t *n)
+{
+    if (!c || !n || g < 0 || g >= (int)c->G.size()) return MR_ERR_ARG;
+    *n = (int64_t)c->G[g].recv_pts.size();
+    return MR_OK;
+}
+
+int mr_receiver_data(mr_ctx *c, int g, const double *const *q, double *out)
+{
+    if (!c || !q || !out || g < 0 || g >= (int)c->G.size()) return MR_ERR_ARG;
+    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_receiver_data before mr_bind_workspace");
+    mrk::StateSrc src[mrk::MAXG] = {};
+    double *outs[mrk::MAXG] = {};
+    for (size_t k = 0; k < c->G.size(); ++k) {
+        src[k].y = q[k];
+        outs[k] = c->G[k].recv_buf;
+    }
+    outs[g] = out;
+    return donor_launch(c, c->G[g].recv_list_d, (int64_t)c->G[g].recv_pts.size(), src, outs);
+}
+
+int mr_timestep(mr_ctx *c, double *h, double *H)
+{
+    if (!c) return MR_ERR_ARG;
+    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_timestep before mr_bind_workspace");
+    double Hm;
+    if (c->P.dt_fixed > 0) {
+        Hm = c->P.dt_fixed;
+    } else {
+        Hm = INFINITY;
+        for (auto &g : c->G) {
+            HIPCHK(c, mrk::launch_dt(g.dev, c->ph, g.y[g.cur], g.dt, c->st));
+            int nb = 256;
+            HIPCHK(c, mrk::launch_reduce(g.npts, g.dt, 0, c->partial, nb, c->st));
+            HIPCHK(c, mrk::launch_reduce(nb, c->partial, 0, c->partial + 512, 1, c->st));
+            double v = 0;
+            HIPCHK(c, hipMemcpyAsync(&v, c->partial + 512, 8, hipMemcpyDeviceToHost, c->st));
+            HIPCHK(c, hipStreamSynchronize(c->st));
+            Hm = std::min(Hm, g.rate * v);
+        }
+        Hm *= c->P.cfl;
+    }
+    if (!(Hm > 0) || !std::isfinite(Hm)) return fail(c, MR_ERR_SETUP, "invalid timestep %g", Hm);
+    c->H = Hm;
+    c->h = Hm / c->rmax;
+    c->have_dt = true;
+    int m = c->P.hist_len;
+    c->c_own.assign(c->G.size(), std::vector<double>(m));
+    c->beta.assign(c->G.size(), {});
+    for (size_t g = 0; g < c->G.size(); ++g) {
+        double Hg = Hm / c->G[g].rate;
+        for (int j = 0; j < m; ++j) c->c_own[g][j] = (double)c->alpha_own[g][j] * Hg;
+        int per = c->rmax / c->G[g].rate;
+        c->beta[g].assign(per, std::vector<double>(m, 0.0));
+        for (int jp = 1; jp < per; ++jp)
+            for (int j = 0; j < m; ++j) c->beta[g][jp][j] = (double)c->alpha_mid[g][jp][j] * Hg;
+    }
+    if (h) *h = c->h;
+    if (H) *H = c->H;
+    return MR_OK;
+}
+
+int mr_mrab_start(mr_ctx *c, double t0)
+{
+    if (!c) return MR_ERR_ARG;
+    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_mrab_start before mr_bind_workspace");
+    if (!c->have_dt) {
+        int rc = mr_timestep(c, nullptr, nullptr);
+        if (rc) return rc;
+    }
+    int m = c->P.hist_len;
+    int G = (int)c->G.size();
+    double d = c->h;
+    int nsteps = (m - 1) * c->rmax;
+    std::vector<const double *> qv(G);
+    std::vector<double *> fv(G);
+    auto stage = [&](int which_q, int k) {   // which_q: 0 = y, 1 = rk[4] (ytmp)
+        for (int g = 0; g < G; ++g) {
+            qv[g] = which_q ? c->G[g].rk[4] : c->G[g].y[c->G[g].cur];
+            fv[g] = c->G[g].rk[k];
+        }
+        return rhs_all(c, qv.data(), fv.data());
+    };
+    for (auto &g : c->G) g.head = m - 1;
+    for (int n = 0; n <= nsteps; ++n) {
+        int rc = stage(0, 0);
+        if (rc) return rc;
+        for (int g = 0; g < G; ++g) {
+            GridHost &Gh = c->G[g];
+            int per = c->rmax / Gh.rate;
+            int back = nsteps - n;
+            if (back % per == 0 && back / per < m) {
+                int j = m - 1 - back / per;
+                HIPCHK(c, hipMemcpyAsync(slot(c, Gh, j), Gh.rk[0], nelem(Gh) * 8, hipMemcpyDeviceToDevice, c->st));
+            }
+        }
+        if (n == nsteps) break;
+        if (c->P.order <= 3) {
+            for (auto &g : c->G) HIPCHK(c, mrk::launch_axpy(nelem(g), g.y[g.cur], d / 3.0, g.rk[0], g.rk[4], c->st));
+            if ((rc = stage(1, 1))) return rc;
+            for (auto &g : c->G)
+                HIPCHK(c, mrk::launch_axpy(nelem(g), g.y[g.cur], 2.0 * d / 3.0, g.rk[1], g.rk[4], c->st));
+            if ((rc = stage(1, 2))) return rc;
+            for (auto &g : c->G)
+                HIPCHK(c, mrk::launch_rk3_final(nelem(g), g.y[g.cur], d / 4.0, g.rk[0], g.rk[2], g.y[g.cur], c->st));
+        } else {
+            for (auto &g : c->G) HIPCHK(c, mrk::launch_axpy(nelem(g), g.y[g.cur], d / 2.0, g.rk[0], g.rk[4], c->st));
+            if ((rc = stage(1, 1))) return rc;
+            for (auto &g : c->G) HIPCHK(c, mrk::launch_axpy(nelem(g), g.y[g.cur], d / 2.0, g.rk[1], g.rk[4], c->st));
+            if ((rc = stage(1, 2))) return rc;
+            for (auto &g : c->G) HIPCHK(c, mrk::launch_axpy(nelem(g), g.y[g.cur], d, g.rk[2], g.rk[4], c->st));
+            if ((rc = stage(1, 3))) return rc;
+            for (auto &g : c->G)
+                HIPCHK(c, mrk::launch_rk4_final(nelem(g), g.y[g.cur], d / 6.0, g.rk[0], g.rk[1], g.rk[2], g.rk[3],
+                                                 g.y[g.cur], c->st));
+        }
+    }
+    // stage every grid's first own step
+    for (size_t g = 0; g < c->G.size(); ++g) {
+        GridHost &Gh = c->G[g];
+        mrk::Combine cb{};
+        cb.m = m;
+        for (int j = 0; j < m; ++j) {
+            cb.c[j] = c->c_own[g][j];
+            cb.hist[j] = slot(c, Gh, j);
+        }
+        cb.y_next = Gh.y[1 - Gh.cur];
+        HIPCHK(c, mrk::launch_combine(nelem(Gh), Gh.y[Gh.cur], cb, c->st));
+    }
+    c->t = t0 + nsteps * d;
+    c->nmacro = 0;
+    c->started = true;
+    return MR_OK;
+}
+
+int mr_mrab_macrostep(mr_ctx *c, int nsteps)
+{
+    if (!c || nsteps < 0) return MR_ERR_ARG;
+    if (!c->started) return fail(c, MR_ERR_STATE, "mr_mrab_macrostep before mr_mrab_start");
+    int m = c->P.hist_len;
+    int G = (int)c->G.size();
+    for (int s = 0; s < nsteps; ++s) {
+        for (int k = 1; k <= c->rmax; ++k) {
+            bool ends[mrk::MAXG];
+            for (int g = 0; g < G; ++g) {
+                ends[g] = k % (c->rmax / c->G[g].rate) == 0;
+                if (ends[g]) c->G[g].cur ^= 1;   // the staged own step becomes current
+            }
+            mrk::StateSrc src[mrk::MAXG] = {};
+            double *out[mrk::MAXG] = {};
+            for (int g = 0; g < G; ++g) {
+                GridHost &Gh = c->G[g];
+                src[g].y = Gh.y[Gh.cur];
+                out[g] = Gh.recv_buf;
+                if (!ends[g]) {
+                    int per = c->rmax / Gh.rate;
+                    src[g].mid = 1;
+                    src[g].m = m;
+                    for (int j = 0; j < m; ++j) {
+                        src[g].beta[j] = c->beta[g][k % per][j];
+                        src[g].hist[j] = slot(c, Gh, j);
+                    }
+                }
+            }
+            int rc = donor_launch(c, c->pat_d[k], (int64_t)c->pat[k].size(), src, out);
+            if (rc) return rc;
+            for (int g = 0; g < G; ++g) {
+                if (!ends[g]) continue;
+                GridHost &Gh = c->G[g];
+                mrk::Combine cb{};
+                cb.m = m;
+                for (int j = 0; j < m - 1; ++j) cb.hist[j] = slot(c, Gh, j + 1);
+                for (int j = 0; j < m; ++j) cb.c[j] = c->c_own[g][j];
+                cb.y_next = Gh.y[1 - Gh.cur];
+                double *Fnew = slot(c, Gh, 0);      // the oldest slot is overwritten
+                rc = grid_rhs(c, g, Gh.y[Gh.cur], Fnew, cb, true);
+                if (rc) return rc;
+                Gh.head = (Gh.head + 1) % m;
+            }
+        }
+        c->t += c->H;
+        c->nmacro++;
+    }
+    return MR_OK;
+}
+
+int mr_get_history(mr_ctx *c, int g, int j, double *out)
+{
+    if (!c || !out || g < 0 || g >= (int)c->G.size() || j < 0 || j >= c->P.hist_len) return MR_ERR_ARG;
+    if (!c->started) return fail(c, MR_ERR_STATE, "mr_get_history before mr_mrab_start");
+    GridHost &G = c->G[g];
+    HIPCHK(c, hipMemcpyAsync(out, slot(c, G, j), nelem(G) * 8, hipMemcpyDeviceToDevice, c->st));
+    return MR_OK;
+}
+
+int mr_time(const mr_ctx *c, double *t, int64_t *ms)
+{
+    if (!c) return MR_ERR_ARG;
+    if (t) *t = c->t;
+    if (ms) *ms = c->nmacro;
+    return MR_OK;
+}
+
+int mr_ab_coeffs(int order, int hist_len, double tau, double *out)
+{
+    if (!out || !(tau > 0.0) || tau > 1.0) return MR_ERR_ARG;
+    std::vector<long double> a;
+    if (!ab_alpha(order, hist_len, (long double)tau, a)) return MR_ERR_ARG;
+    for (int j = 0; j < hist_len; ++j) out[j] = (double)a[j];
+    return MR_OK;
+}
+
+int mr_kernel_timing(mr_ctx *c, int grid, int max_events)
+{
+    if (!c || grid < -1 || grid >= (int)c->G.size() || max_events < 0) return MR_ERR_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    for (auto e : c->ev) (void)hipEventDestroy(e);
+    c->ev.clear();
+    c->tgrid = max_events ? grid : -1;
+    c->tmax = max_events;
+    c->tcount = 0;
+    for (int i = 0; i < 2 * max_events; ++i) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        c->ev.push_back(e);
+    }
+    return MR_OK;
+}
+
+int mr_kernel_time(mr_ctx *c, double *total_ms, int *count)
+{
+    if (!c || !total_ms || !count) return MR_ERR_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    double tot = 0;
+    for (int i = 0; i < c->tcount; ++i) {
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+        tot += ms;
+    }
+    *total_ms = tot;
+    *count = c->tcount;
+    return MR_OK;
+}
+
+int mr_guard(mr_ctx *c, double *maxabs)
+{
+    if (!c) return MR_ERR_ARG;
+    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_guard before mr_bind_workspace");
+    double mx = 0;
+    for (auto &g : c->G) {
+        HIPCHK(c, mrk::launch_reduce(nelem(g), g.y[g.cur], 1, c->partial, 256, c->st));
+        HIPCHK(c, mrk::launch_reduce(256, c->partial, 1, c->partial + 512, 1, c->st));
+        double v = 0;
+        HIPCHK(c, hipMemcpyAsync(&v, c->partial + 512, 8, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(c, hipStreamSynchronize(c->st));
+        mx = std::max(mx, v);
+    }
+    if (maxabs) *maxabs = mx;
+    if (!std::isfinite(mx)) return fail(c, MR_ERR_NONFINITE, "non-finite value in a state");
+    return MR_OK;
+}
+
+const char *mr_last_error(const mr_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+void mr_destroy(mr_ctx *c)
+{
+    if (!c) return;
+    if (c->st || true) (void)hipStreamSynchronize(c->st);
+    for (auto e : c->ev) (void)hipEventDestroy(e);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,214 @@
+"""Python front end of libmrab.so: one overset system on one GPU.
+
+PyTorch provides the device memory (one workspace tensor, the state tensors)
+and the stream; every step of the right-hand side and of the time integration
+runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import POINTER, byref, c_double, c_int, c_int8, c_int64, c_size_t, c_void_p
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from . import assemble
+
+CART, CURV = 0, 1
+
+
+def _params(wl) -> _lib.MrParams:
+    P = wl.params
+    p = _lib.MrParams()
+    p.dim = wl.dim
+    p.sbp = int(P["sbp"])
+    p.order = int(P["order"])
+    p.hist_len = int(P["hist_len"])
+    p.interp_width = int(P["interp_width"])
+    p.gamma, p.Re, p.Pr, p.mu = P["gamma"], P["Re"], P["Pr"], P["mu"]
+    p.lambda_over_mu = P["lambda_over_mu"]
+    p.sigma_I_iface, p.sigma_I_bc = P["sigma_I_iface"], P["sigma_I_bc"]
+    p.T_wall, p.wall_visc = P["T_wall"], P["wall_visc"]
+    for i in range(5):
+        p.q_inf[i] = P["q_inf"][i] if i < len(P["q_inf"]) else 0.0
+    p.cfl = P["cfl"]
+    p.dt_fixed = P.get("dt_fixed", 0.0)
+    return p
+
+
+class System:
+    """An overset problem assembled on the GPU.
+
+    ``wl`` is a problem description (see the ``workloads`` package): grids,
+    boundary flags, hole shapes, rates, parameters and initial states.
+    """
+
+    def __init__(self, wl, device: str = "cuda:0", stream: Optional[torch.cuda.Stream] = None):
+        self.lib = _lib.load()
+        self.wl = wl
+        self.device = torch.device(device)
+        self.dim, self.nv = wl.dim, wl.dim + 2
+        self.RB = self.nv + self.dim * (self.nv - 1)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._params = _params(wl)
+        self.ctx = c_void_p()
+        _lib.check(self.lib.mr_create(byref(self._params), c_void_p(self.stream.cuda_stream), byref(self.ctx)),
+                   None, "mr_create")
+        self.iblanks = []
+        self._keep = []
+        for g in wl.grids:
+            ib = assemble.iblank(g)
+            self.iblanks.append(ib)
+            d = _lib.MrGridDesc()
+            for k in range(3):
+                d.n[k] = g.n[k] if k < g.dim else 1
+                d.periodic[k] = int(g.periodic[k]) if k < g.dim else 0
+                d.origin[k] = g.origin[k] if k < len(g.origin) else 0.0
+                d.spacing[k] = g.spacing[k] if k < len(g.spacing) else 1.0
+            d.kind = CURV if g.kind == 1 else CART
+            if g.kind == 1:
+                coords = np.ascontiguousarray(g.coords, dtype=np.float64)
+                self._keep.append(coords)
+                d.coords = coords.ctypes.data_as(POINTER(c_double))
+                per = g.coord_period or [(0.0, 0.0), (0.0, 0.0)]
+                for a in range(len(per)):
+                    for b in range(len(per[a])):
+                        d.coord_period[a][b] = per[a][b]
+            self._keep.append(ib)
+            d.iblank = ib.ctypes.data_as(POINTER(c_int8))
+            for k in range(2 * g.dim):
+                d.face_bc[k] = g.face_bc[k]
+            d.rate = g.rate
+            gid = c_int()
+            self._check(self.lib.mr_add_grid(self.ctx, byref(d), byref(gid)), "mr_add_grid")
+        W = int(wl.params["interp_width"])
+        self.recv_pts = [assemble.receivers(g, ib) for g, ib in zip(wl.grids, self.iblanks)]
+        self.donor_tables = assemble.donors(wl.grids, self.iblanks, self.recv_pts, W)
+        S = W ** self.dim
+        for g, tab in enumerate(self.donor_tables):
+            for dg, (rp, pts, w) in tab.items():
+                rp = np.ascontiguousarray(rp, dtype=np.int64)
+                pts = np.ascontiguousarray(pts, dtype=np.int64)
+                w = np.ascontiguousarray(w, dtype=np.float64)
+                self._check(self.lib.mr_set_overset(self.ctx, g, dg, len(rp), S,
+                                                     rp.ctypes.data_as(POINTER(c_int64)),
+                                                     pts.ctypes.data_as(POINTER(c_int64)),
+                                                     w.ctypes.data_as(POINTER(c_double))), "mr_set_overset")
+        # receiver row order inside the library: registration order
+        self.recv_order = []
+        for g, tab in enumerate(self.donor_tables):
+            order = []
+            for dg, (rp, _, _) in tab.items():
+                order.extend(rp.tolist())
+            self.recv_order.append(np.array(order, dtype=np.int64))
+        nbytes = c_size_t()
+        self._check(self.lib.mr_finalize(self.ctx, byref(nbytes)), "mr_finalize")
+        self.ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        self._check(self.lib.mr_bind_workspace(self.ctx, c_void_p(base + off), c_size_t(nbytes.value)),
+                    "mr_bind_workspace")
+        self.set_states([torch.as_tensor(q, dtype=torch.float64) for q in wl.q0])
+
+    # ------------------------------------------------------------ helpers
+    def _check(self, rc, what):
+        _lib.check(rc, self.ctx, what)
+
+    def _dev(self, q) -> torch.Tensor:
+        t = torch.as_tensor(q, dtype=torch.float64)
+        return t.to(self.device).contiguous()
+
+    @property
+    def ngrids(self):
+        return len(self.wl.grids)
+
+    def npts(self, g):
+        return self.wl.grids[g].npts
+
+    # -------------------------------------------------------------- state
+    def set_states(self, states: List) -> None:
+        self._states_keep = [self._dev(q).reshape(self.nv, -1) for q in states]
+        for g, t in enumerate(self._states_keep):
+            self._check(self.lib.mr_set_state(self.ctx, g, c_void_p(t.data_ptr())), "mr_set_state")
+
+    def state(self, g: int) -> torch.Tensor:
+        out = torch.empty((self.nv, self.npts(g)), dtype=torch.float64, device=self.device)
+        self._check(self.lib.mr_get_state(self.ctx, g, c_void_p(out.data_ptr())), "mr_get_state")
+        return out
+
+    # ---------------------------------------------------------------- rhs
+    def rhs(self, states: List, t: float = 0.0) -> List[torch.Tensor]:
+        qs = [self._dev(q).reshape(self.nv, -1) for q in states]
+        outs = [torch.empty_like(q) for q in qs]
+        qa = (c_void_p * len(qs))(*[q.data_ptr() for q in qs])
+        oa = (c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        self._check(self.lib.mr_rhs(self.ctx, t, qa, oa), "mr_rhs")
+        self._alive = (qs, outs)
+        return outs
+
+    def receiver_data(self, g: int, states: List) -> torch.Tensor:
+        """Receiver rows of grid g, in ascending receiver point order."""
+        qs = [self._dev(q).reshape(self.nv, -1) for q in states]
+        n = c_int64()
+        self._check(self.lib.mr_num_receivers(self.ctx, g, byref(n)), "mr_num_receivers")
+        out = torch.zeros((max(n.value, 1), self.RB), dtype=torch.float64, device=self.device)
+        qa = (c_void_p * len(qs))(*[q.data_ptr() for q in qs])
+        self._check(self.lib.mr_receiver_data(self.ctx, g, qa, c_void_p(out.data_ptr())), "mr_receiver_data")
+        self._alive = (qs, out)
+        out = out[: n.value]
+        perm = np.argsort(self.recv_order[g], kind="stable")
+        return out[torch.as_tensor(perm, device=self.device)]
+
+    # --------------------------------------------------------- integrate
+    def timestep(self):
+        h, H = c_double(), c_double()
+        self._check(self.lib.mr_timestep(self.ctx, byref(h), byref(H)), "mr_timestep")
+        return h.value, H.value
+
+    def start(self, t0: float = 0.0):
+        self._check(self.lib.mr_mrab_start(self.ctx, t0), "mr_mrab_start")
+
+    def macrostep(self, n: int = 1):
+        self._check(self.lib.mr_mrab_macrostep(self.ctx, n), "mr_mrab_macrostep")
+
+    def history(self, g: int, j: int) -> torch.Tensor:
+        out = torch.empty((self.nv, self.npts(g)), dtype=torch.float64, device=self.device)
+        self._check(self.lib.mr_get_history(self.ctx, g, j, c_void_p(out.data_ptr())), "mr_get_history")
+        return out
+
+    def time(self):
+        t, k = c_double(), c_int64()
+        self._check(self.lib.mr_time(self.ctx, byref(t), byref(k)), "mr_time")
+        return t.value, k.value
+
+    def guard(self) -> float:
+        v = c_double()
+        self._check(self.lib.mr_guard(self.ctx, byref(v)), "mr_guard")
+        return v.value
+
+    def kernel_timing(self, grid: int, max_events: int):
+        self._check(self.lib.mr_kernel_timing(self.ctx, grid, max_events), "mr_kernel_timing")
+
+    def kernel_time(self):
+        ms, n = c_double(), c_int()
+        self._check(self.lib.mr_kernel_time(self.ctx, byref(ms), byref(n)), "mr_kernel_time")
+        return ms.value, n.value
+
+    def close(self):
+        if self.ctx:
+            self.lib.mr_destroy(self.ctx)
+            self.ctx = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ab_coeffs(order: int, hist_len: int, tau: float = 1.0) -> np.ndarray:
+    out = (c_double * hist_len)()
+    _lib.check(_lib.load().mr_ab_coeffs(order, hist_len, tau, out), None, "mr_ab_coeffs")
+    return np.array(out[:])
