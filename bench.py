@@ -1,0 +1,271 @@
+"""Benchmark: multi-rate vs single-rate Adams-Bashforth on the cylinder-like
+overset workload, one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-equal-error]
+
+Workload (synthetic stand-in for the paper's cylinder case): a 512 x 512
+Cartesian background on [-20, 20]^2 with far-field faces and a hole r < 2, and
+a 256 x 128 body-fitted O-mesh (r = 0.5..3, stretching 1.03) with an
+isothermal no-slip wall; Mach 0.2, Re 200, Pr 0.72, seeded 1e-3 perturbation
+of u; SBP 4-2, cubic donors, fourth-order AB, rate ratio 4 (O-mesh 4 steps per
+background step).
+
+A step is one macrostep of the whole path (donor gather + per-grid fused
+right-hand side, SAT and AB update for every evaluating grid).  The timed
+region holds exactly K macrosteps with the states already in device memory.
+value = MRAB point-updates per second = sum_l r_l * N_l(active) * K / time.
+
+Also reported: the single-rate AB (every grid at the fast step) rate, the
+errors of both against a single-rate reference at a 4x smaller step (equal
+error check), the roofline of the dominant kernel (the background grid's
+right-hand-side step, timed with HIP events on the library's stream inside
+the timed region), and the CPU oracle on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(rates=(1, 4)):
+    import workloads
+    wl = workloads.cylinder()
+    wl.grids[0].rate, wl.grids[1].rate = rates
+    return wl
+
+
+def active_counts(sysg):
+    return [int(ib.sum()) for ib in sysg.iblanks]
+
+
+def bytes_per_point(wl, g):
+    """Algorithmic bytes per point of one fused right-hand-side + AB update:
+    read the state, read m-1 older history values, write the new right-hand
+    side, write the next state (nv doubles each), plus 5 metric doubles on
+    curvilinear 2D grids."""
+    nv = wl.dim + 2
+    m = wl.params["hist_len"]
+    b = 8 * nv * (m + 2)
+    if wl.grids[g].kind == 1:
+        b += 8 * (wl.dim * wl.dim + 1)
+    return b
+
+
+def run_gpu(args):
+    import torch
+    from paper_1805_06607_amd.system import System
+
+    res = {}
+    # ---------------------------------------------------------------- MRAB
+    wl = workload((1, 4))
+    log("setup MRAB system")
+    mr = System(wl)
+    h, H = mr.timestep()
+    mr.start(0.0)
+    n_act = active_counts(mr)
+    rates = [g.rate for g in wl.grids]
+    pts_per_step = sum(r * n for r, n in zip(rates, n_act))
+    mr.macrostep(args.warmup)
+    mr.kernel_timing(0, args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mr.macrostep(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dt_mrab = t1 - t0
+    ktot_ms, kcount = mr.kernel_time()
+    mr.guard()
+    log(f"MRAB {args.steps} macrosteps: {dt_mrab * 1e3:.2f} ms, kernel {ktot_ms:.3f} ms over {kcount}")
+    res["mrab"] = dict(time_s=dt_mrab, pts_per_step=pts_per_step, H=H, h=h)
+    # roofline of the dominant kernel (background grid right-hand-side step)
+    bpp = bytes_per_point(wl, 0)
+    per_launch = n_act[0] * bpp
+    avg_s = (ktot_ms / max(kcount, 1)) * 1e-3
+    achieved = per_launch / avg_s / 1e9
+    res["roofline"] = {
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "kernel": "k_rhs_tile2d on the background grid (fused gradients, flux divergence, SAT, "
+                  "AB update)",
+        "bytes_per_launch": per_launch, "bytes_per_point": bpp, "points": n_act[0],
+        "avg_launch_us": avg_s * 1e6, "launches_timed": kcount,
+    }
+    del mr
+    # ---------------------------------------------------------------- SRAB
+    wls = workload((1, 1))
+    wls.params["dt_fixed"] = h            # every grid at the fast step
+    log("setup SRAB system")
+    sr = System(wls)
+    sr.timestep()
+    sr.start(0.0)
+    sr.macrostep(args.warmup)
+    torch.cuda.synchronize()
+    nsr = args.steps * 4
+    t0 = time.perf_counter()
+    sr.macrostep(nsr)
+    torch.cuda.synchronize()
+    dt_srab = time.perf_counter() - t0
+    srab_pts = sum(n_act) * nsr
+    log(f"SRAB {nsr} steps: {dt_srab * 1e3:.2f} ms")
+    res["srab"] = dict(time_s=dt_srab, steps=nsr, pts=srab_pts)
+    del sr
+    # -------------------------------------------------------- equal error
+    if not args.no_equal_error:
+        res["equal_error"] = equal_error(args, h)
+    return res, wl, n_act
+
+
+def equal_error(args, h):
+    """MRAB (macrostep 4h, O-mesh at h) and single-rate AB (every grid at h)
+    against a single-rate reference at h/4, all from the same initial state
+    and stopped at the same final time T = 4h (m - 1 + N) (each bootstrap
+    spans m - 1 of its own macrosteps); error = max |rho - rho_ref| over
+    active points of both grids (the paper's error measure for its
+    convergence tables).  Wall time covers the macrosteps only."""
+    import torch
+    from paper_1805_06607_amd.system import System
+    N = args.ee_macrosteps
+    wl0 = workload((1, 4))
+    m = wl0.params["hist_len"]
+
+    # common start: the impulsive start (uniform flow meeting a no-slip wall) is
+    # first developed by a single-rate run at h/4, so that the bootstraps of
+    # the compared runs see a smooth solution
+    spin = workload((1, 1))
+    spin.params["dt_fixed"] = h / 4
+    s = System(spin)
+    s.timestep()
+    s.start(0.0)
+    s.macrostep(args.ee_spinup)
+    q_start = [s.state(g).cpu().numpy() for g in range(2)]
+    del s
+
+    def run(rates, H, nsteps):
+        wl = workload(rates)
+        wl.q0 = [q.copy() for q in q_start]
+        wl.params["dt_fixed"] = H
+        s = System(wl)
+        s.timestep()
+        s.start(0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.macrostep(nsteps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        t, _ = s.time()
+        rho = [s.state(g)[0].cpu().numpy() for g in range(2)]
+        ib = [x.astype(bool) for x in s.iblanks]
+        del s
+        return rho, ib, el, t
+
+    ref, ib, el_ref, t_ref = run((1, 1), h / 4, 15 * (m - 1) + 16 * N)
+    rho_m, _, el_m, t_m = run((1, 4), 4 * h, N)
+    rho_s, _, el_s, t_s = run((1, 1), h, 3 * (m - 1) + 4 * N)
+
+    def err(rho):
+        return max(float(np.max(np.abs(rho[g] - ref[g])[ib[g]])) for g in range(2))
+
+    e_m, e_s = err(rho_m), err(rho_s)
+    log(f"equal error: T={t_ref:.6g} (mrab {t_m:.6g}, srab {t_s:.6g}); err mrab {e_m:.3e} srab {e_s:.3e}; "
+        f"wall mrab {el_m:.4f}s srab {el_s:.4f}s")
+    return {"T": t_ref, "mrab_macrosteps": N, "spinup_steps_at_h_over_4": args.ee_spinup, "err_mrab": e_m, "err_srab": e_s,
+            "wall_s_mrab": el_m, "wall_s_srab": el_s, "wall_ratio_srab_over_mrab": el_s / el_m,
+            "reference": "single-rate AB at h/4", "error": "max |rho - rho_ref| over active points"}
+
+
+def cpu_baseline(args):
+    """The oracle (plain C + numpy, OpenMP) on a bounded sample of the same
+    workload: MRAB macrosteps from a history of repeated F(y0), timed until
+    ~10 s of work."""
+    import oracle
+    wl = workload((1, 4))
+    orc = oracle.OracleSystem(wl)
+    h, H = orc.timestep()
+    mr = orc.integrator(H)
+    F0 = orc.rhs(wl.q0)
+    m = wl.params["hist_len"]
+    mr.set_history(wl.q0, [[F0[g]] * m for g in range(2)], 0.0)
+    n_act = [int(g.iblank.sum()) for g in orc.grids]
+    pts = sum(g.rate * n for g, n in zip(wl.grids, n_act))
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        mr.macrostep()
+        k += 1
+        if time.perf_counter() - t0 > args.cpu_seconds and k >= 2:
+            break
+    el = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return {"value": pts * k / el, "unit": "pt-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{k} MRAB macrosteps of the same cylinder workload (full size) from a "
+                      f"constant history, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-equal-error", action="store_true")
+    ap.add_argument("--ee-macrosteps", type=int, default=200)
+    ap.add_argument("--ee-spinup", type=int, default=2000)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the method's work here has no multi-GPU path "
+              "(see the sharding design notes); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    res, wl, n_act = run_gpu(args)
+    K = args.steps
+    t = res["mrab"]["time_s"]
+    value = res["mrab"]["pts_per_step"] * K / t
+    line = {
+        "metric": "MRAB pt-updates/s & HBM roofline frac vs single-rate AB at equal error, 1 GPU",
+        "value": value,
+        "unit": "pt-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": t / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "cylinder-like overset: 512x512 Cartesian background (far field, hole r<2) + "
+                        "256x128 O-mesh (wall), SBP 4-2, cubic donors, AB4 MRAB ratio 4, Re 200, M 0.2",
+            "points_active": n_act, "rates": [g.rate for g in wl.grids],
+            "H": res["mrab"]["H"], "h": res["mrab"]["h"],
+        },
+        "roofline": res["roofline"],
+        "srab": {
+            "value": res["srab"]["pts"] / res["srab"]["time_s"],
+            "ms_per_macrostep_equivalent": res["srab"]["time_s"] / res["srab"]["steps"] * 4 * 1e3,
+            "mrab_speedup_same_fast_step": (res["srab"]["time_s"] / (res["srab"]["steps"] / 4)) / (t / K),
+        },
+        "equivalent_single_rate_pt_updates_per_s": max(g.rate for g in wl.grids) * sum(n_act) * K / t,
+    }
+    if "equal_error" in res:
+        line["equal_error"] = res["equal_error"]
+    if not args.no_cpu:
+        log("cpu baseline")
+        line["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -53,28 +53,29 @@ struct StateSrc {
     const double *hist[MAXH];
 };
 
-struct Phys;
-struct DonorLaunch {
-    const GridDev *grids;      // device array of all grid descriptors
-    StateSrc src[MAXG];
-    double *out[MAXG];         // receiver buffers per receiving grid
-    const int32_t *recv_list;  // global receiver ids of this launch
-    const int32_t *recv_grid;  // per global receiver: receiving grid
-    const int32_t *recv_row;   // per global receiver: row in its grid's buffer
-    const int8_t *ent_grid;    // per (receiver, entry): donor grid
-    const int32_t *ent_pt;     // per (receiver, entry): donor point
-    const double *ent_w;       // per (receiver, entry): weight
-    int64_t nrecv;
-    int S;                     // entries per receiver (power of two, <= 64)
-    int dim, nv, sbp;
+// donor gather of one link (receivers of one grid taking data from one donor
+// grid): lanes (receiver k, entry e), k < nrecv, e < S
+struct DonorLink {
+    GridDev g;                 // donor grid
+    StateSrc src;              // donor state (extrapolated when mid-step)
     Phys ph;
+    double *out;               // receiving grid's receiver rows
+    int32_t row0;              // row of the link's first receiver
+    const int32_t *pts;        // nrecv x S donor points
+    const double *w;           // nrecv x S weights
+    int64_t nrecv;
+    int S;
+    int sbp;
 };
 
 // ---------------------------------------------------------------- launches
 hipError_t launch_grad(const GridDev &g, int sbp, double gm1, const double *q, double *grad, hipStream_t st);
 hipError_t launch_rhs(const GridDev &g, const GridDev *g_dev, int sbp, const Phys &ph, const double *q,
                       const double *grad, double *F, const Combine &cb, hipStream_t st);
-hipError_t launch_donor(const DonorLaunch &a, hipStream_t st);
+hipError_t launch_donor(const DonorLink &a, hipStream_t st);
+// fused LDS-tiled 2D right-hand side (gradients, fluxes, divergence, SAT, AB update)
+hipError_t launch_rhs_tile2d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *F,
+                             const Combine &cb, hipStream_t st);
 hipError_t launch_combine(int64_t n, const double *y, const Combine &cb, hipStream_t st);
 hipError_t launch_axpy(int64_t n, const double *y, double a, const double *x, double *out, hipStream_t st);
 hipError_t launch_rk3_final(int64_t n, const double *y, double a, const double *k1, const double *k3,

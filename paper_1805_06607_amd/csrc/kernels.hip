@@ -432,9 +432,316 @@ __global__ void __launch_bounds__(256) k_rhs(GridDev g, Phys ph, const double *_
         for (int v = 0; v < NV; ++v) {
             int64_t e = v * N + p;
             double acc = q[e];
-            for (int j = 0; j < cb.m - 1; ++j) acc = add_nc(acc, cb.c[j], cb.hist[j][e]);
+#pragma unroll
+            for (int j = 0; j < MAXH - 1; ++j)
+                if (j < cb.m - 1) acc = add_nc(acc, cb.c[j], cb.hist[j][e]);
             acc = add_nc(acc, cb.c[cb.m - 1], r[v]);
             cb.y_next[e] = acc;
+        }
+    }
+}
+
+// ------------------------------------------- fused LDS-tiled 2D right-hand side
+// One workgroup of 256 threads computes a 32 x 8 tile of outputs in one pass:
+//   1. primitives (rho, u, v, T) and class bytes on the tile plus a halo of HP
+//      points, metric terms on the flux region, all staged in LDS (every
+//      global load of the phase is issued before the first use);
+//   2. for xi then eta: the contravariant flux of that direction on the tile
+//      plus HF points along it (gradients from the LDS primitives) in LDS,
+//      then its SBP derivative at the outputs;
+//   3. epilogue per output: scale, SAT penalties, store F, AB update.
+// A first-derivative row reaches at most R = 3 points (SBP 4-2 closures; 1
+// for SBP 2-1), so outputs need fluxes within HF = R and every flux point of
+// that region has its whole stencil inside HP = HF + R, whatever the run
+// layout.
+template <int SBP>
+struct TileCfg {
+    static constexpr int TX = 32, TY = 8, NT = 256;
+    static constexpr int R = SBP == 42 ? 3 : 1;
+    static constexpr int HF = R, HP = 2 * R;
+    static constexpr int PX = TX + 2 * HP, PY = TY + 2 * HP, PN = PX * PY;
+    static constexpr int MX = TX + 2 * HF, MY = TY + 2 * HF, MN = MX * MY;   // metric region
+    static constexpr int FN = (TX + 2 * HF) * TY > TX * (TY + 2 * HF) ? (TX + 2 * HF) * TY : TX * (TY + 2 * HF);
+    static constexpr int NIT = (PN + NT - 1) / NT;
+};
+
+template <int SBP, int CART>
+__global__ void __launch_bounds__(256) k_rhs_tile2d(GridDev g, Phys ph, const double *__restrict__ q,
+                                                    double *__restrict__ F, Combine cb, int ntx, int nty)
+{
+    using C = TileCfg<SBP>;
+    constexpr int TX = C::TX, TY = C::TY, HF = C::HF, HP = C::HP, PX = C::PX, PY = C::PY, PN = C::PN;
+    constexpr int MX = C::MX, MN = C::MN;
+    __shared__ double sP[4][PY][PX];                 // rho, u, v, T
+    __shared__ double sF[4][C::FN];                  // contravariant flux of one direction
+    __shared__ double sM[CART ? 1 : 5][CART ? 1 : MN];   // M00 M01 M10 M11 J on the flux region
+    __shared__ int8_t sC[2][PY][PX];                 // class bytes
+
+    // XCD-aware order: consecutive workgroups go to different XCDs, so give
+    // each XCD a contiguous range of tiles (neighbours share halos in its L2);
+    // a bijection when the tile count is a multiple of 8, identity otherwise
+    const int nblk = ntx * nty;
+    const int b = blockIdx.x;
+    const int tile = (nblk % 8) ? b : (b % 8) * (nblk / 8) + b / 8;
+    const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
+    const int nx = g.n[0], ny = g.n[1];
+    const int64_t N = g.npts;
+    const double gm1 = ph.gamma - 1.0;
+    const int tid = threadIdx.x;
+
+    // 1. stage: issue every load first
+    double lq[C::NIT][4];
+    int8_t lc[C::NIT][2];
+#pragma unroll
+    for (int it = 0; it < C::NIT; ++it) {
+        int e = tid + it * 256;
+        lq[it][0] = lq[it][1] = lq[it][2] = lq[it][3] = 0.0;
+        lc[it][0] = lc[it][1] = (int8_t)CLS_HOLE;
+        if (e < PN) {
+            int cx = e % PX, cy = e / PX;
+            int gx = x0 - HP + cx, gy = y0 - HP + cy;
+            bool ok = true;
+            if (g.periodic[0]) gx = (gx % nx + nx) % nx; else ok = ok && gx >= 0 && gx < nx;
+            if (g.periodic[1]) gy = (gy % ny + ny) % ny; else ok = ok && gy >= 0 && gy < ny;
+            if (ok) {
+                int64_t p = (int64_t)gy * nx + gx;
+                lc[it][0] = g.cls[p];
+                lc[it][1] = g.cls[N + p];
+                lq[it][0] = q[p];
+                lq[it][1] = q[N + p];
+                lq[it][2] = q[2 * N + p];
+                lq[it][3] = q[3 * N + p];
+            }
+        }
+    }
+    if constexpr (!CART) {
+        for (int e = tid; e < MN; e += 256) {
+            int mx = e % MX, my = e / MX;
+            int gx = x0 - HF + mx, gy = y0 - HF + my;
+            bool ok = true;
+            if (g.periodic[0]) gx = (gx % nx + nx) % nx; else ok = ok && gx >= 0 && gx < nx;
+            if (g.periodic[1]) gy = (gy % ny + ny) % ny; else ok = ok && gy >= 0 && gy < ny;
+            int64_t p = ok ? (int64_t)gy * nx + gx : 0;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sM[k][e] = ok ? g.metric[k * N + p] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < C::NIT; ++it) {
+        int e = tid + it * 256;
+        if (e < PN) {
+            int cx = e % PX, cy = e / PX;
+            double r0 = 0.0, u = 0.0, v = 0.0, T = 0.0;
+            if ((lc[it][0] & 15) != CLS_HOLE) {
+                double ri = 1.0 / lq[it][0];
+                u = lq[it][1] * ri;
+                v = lq[it][2] * ri;
+                double pr = gm1 * (lq[it][3] - 0.5 * (u * lq[it][1] + v * lq[it][2]));
+                r0 = lq[it][0];
+                T = pr * ri;
+            }
+            sP[0][cy][cx] = r0;
+            sP[1][cy][cx] = u;
+            sP[2][cy][cx] = v;
+            sP[3][cy][cx] = T;
+            sC[0][cy][cx] = lc[it][0];
+            sC[1][cy][cx] = lc[it][1];
+        }
+    }
+    __syncthreads();
+
+    // metric terms of box cell (cx, cy) (flux region only)
+    auto metric_at = [&](int cx, int cy, int k) -> double {
+        if constexpr (CART) {
+            return 0.0;
+        } else {
+            return sM[k][(cy - (HP - HF)) * MX + (cx - (HP - HF))];
+        }
+    };
+
+    // gradient of (u, v, T) at box cell (cx, cy)
+    auto grad_at = [&](int cx, int cy, double gr[3][2]) {
+        int rx = sC[0][cy][cx] & 15, ry = sC[1][cy][cx] & 15;
+        Vec<3> dx = dsbp<SBP, 3>(rx, [&](int o) {
+            Vec<3> r;
+            r.v[0] = sP[1][cy][cx + o]; r.v[1] = sP[2][cy][cx + o]; r.v[2] = sP[3][cy][cx + o];
+            return r;
+        });
+        Vec<3> dy = dsbp<SBP, 3>(ry, [&](int o) {
+            Vec<3> r;
+            r.v[0] = sP[1][cy + o][cx]; r.v[1] = sP[2][cy + o][cx]; r.v[2] = sP[3][cy + o][cx];
+            return r;
+        });
+        if constexpr (CART) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) { gr[a][0] = g.inv_h[0] * dx.v[a]; gr[a][1] = g.inv_h[1] * dy.v[a]; }
+        } else {
+            double M00 = metric_at(cx, cy, 0), M01 = metric_at(cx, cy, 1);
+            double M10 = metric_at(cx, cy, 2), M11 = metric_at(cx, cy, 3), J = metric_at(cx, cy, 4);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                gr[a][0] = J * (M00 * dx.v[a] + M10 * dy.v[a]);
+                gr[a][1] = J * (M01 * dx.v[a] + M11 * dy.v[a]);
+            }
+        }
+    };
+
+    // contravariant flux of direction m at box cell (cx, cy)
+    auto flux_at = [&](int m, int cx, int cy, double *out) {
+        double gr[3][2];
+        grad_at(cx, cy, gr);
+        double rho = sP[0][cy][cx], uu[2] = {sP[1][cy][cx], sP[2][cy][cx]}, T = sP[3][cy][cx];
+        double pr = rho * T;
+        double rE = pr / gm1 + 0.5 * rho * (uu[0] * uu[0] + uu[1] * uu[1]);
+        double Fv[2][3];
+        viscous_flux<2>(ph, uu, gr, Fv);
+        if constexpr (CART) {
+            out[0] = rho * uu[m];
+            out[1] = rho * uu[0] * uu[m] + (m == 0 ? pr : 0.0) - Fv[m][0];
+            out[2] = rho * uu[1] * uu[m] + (m == 1 ? pr : 0.0) - Fv[m][1];
+            out[3] = (rE + pr) * uu[m] - Fv[m][2];
+        } else {
+            double M0 = metric_at(cx, cy, 2 * m), M1 = metric_at(cx, cy, 2 * m + 1);
+            double U = M0 * uu[0] + M1 * uu[1];
+            out[0] = rho * U;
+            out[1] = rho * uu[0] * U + M0 * pr - (M0 * Fv[0][0] + M1 * Fv[1][0]);
+            out[2] = rho * uu[1] * U + M1 * pr - (M0 * Fv[0][1] + M1 * Fv[1][1]);
+            out[3] = (rE + pr) * U - (M0 * Fv[0][2] + M1 * Fv[1][2]);
+        }
+    };
+
+    // the output point of this thread
+    const int tx = tid % TX, ty = tid / TX;
+    const int cxo = HP + tx, cyo = HP + ty;
+    const int gxo = x0 + tx, gyo = y0 + ty;
+    const bool inside = gxo < nx && gyo < ny;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int FX = m == 0 ? TX + 2 * HF : TX;
+        const int FY = m == 0 ? TY : TY + 2 * HF;
+        const int ox = m == 0 ? HF : 0, oy = m == 0 ? 0 : HF;
+        for (int e = tid; e < FX * FY; e += 256) {
+            int fx = e % FX, fy = e / FX;
+            int cx = HP - ox + fx, cy = HP - oy + fy;
+            double f[4] = {0.0, 0.0, 0.0, 0.0};
+            if ((sC[0][cy][cx] & 15) != CLS_HOLE) flux_at(m, cx, cy, f);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sF[v][e] = f[v];
+        }
+        __syncthreads();
+        if (inside) {
+            int row = sC[m][cyo][cxo] & 15;
+            if (row != CLS_HOLE) {
+                Vec<4> d = dsbp<SBP, 4>(row, [&](int o) {
+                    int fx = m == 0 ? tx + HF + o : tx;
+                    int fy = m == 0 ? ty : ty + HF + o;
+                    int e = fy * FX + fx;
+                    Vec<4> r;
+                    r.v[0] = sF[0][e]; r.v[1] = sF[1][e]; r.v[2] = sF[2][e]; r.v[3] = sF[3][e];
+                    return r;
+                });
+                double sc = CART ? g.inv_h[m] : 1.0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] += sc * d.v[v];
+            }
+        }
+        __syncthreads();
+    }
+
+    // 3. epilogue
+    if (!inside) return;
+    const int64_t p = (int64_t)gyo * nx + gxo;
+    const int cx0 = sC[0][cyo][cxo], cy0 = sC[1][cyo][cxo];
+    double r[4];
+    if ((cx0 & 15) == CLS_HOLE) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) r[v] = 0.0;
+    } else {
+        double J = CART ? 1.0 : metric_at(cxo, cyo, 4);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) r[v] = -J * acc[v];
+        if (((cx0 >> 4) & 3) | ((cy0 >> 4) & 3)) {
+            double qp[4];
+            load_q<2>(q, N, p, qp);
+            double gr[3][2];
+            grad_at(cxo, cyo, gr);
+            double uu[2] = {sP[1][cyo][cxo], sP[2][cyo][cxo]};
+            double Fv[2][3];
+            viscous_flux<2>(ph, uu, gr, Fv);
+            for (int m = 0; m < 2; ++m) {
+                int c = m == 0 ? cx0 : cy0;
+                int bc = (c >> 4) & 3;
+                if (!bc) continue;
+                int sgn = ((c & 15) == 1) ? 1 : -1;
+                double kap[2];
+                if constexpr (CART) {
+                    kap[0] = m == 0 ? g.inv_h[0] : 0.0;
+                    kap[1] = m == 1 ? g.inv_h[1] : 0.0;
+                } else {
+                    double Jp = metric_at(cxo, cyo, 4);
+                    kap[0] = Jp * metric_at(cxo, cyo, 2 * m);
+                    kap[1] = Jp * metric_at(cxo, cyo, 2 * m + 1);
+                }
+                double k2 = kap[0] * kap[0] + kap[1] * kap[1];
+                double dQ[4], dV[4], s2[4] = {0.0, 0.0, 0.0, 0.0};
+                double sigI, sig1 = ph.mu * k2 / (2.0 * ph.Re);
+                bool use_s2 = true;
+#pragma unroll
+                for (int v = 1; v < 4; ++v) s2[v] = kap[0] * Fv[0][v - 1] + kap[1] * Fv[1][v - 1];
+                if (bc == 1) {
+                    const double *rb = g.recv + (int64_t)g.recv_idx[p] * 10;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) { dQ[v] = qp[v] - rb[v]; dV[v] = dQ[v]; }
+#pragma unroll
+                    for (int v = 1; v < 4; ++v) s2[v] -= kap[0] * rb[4 + (v - 1)] + kap[1] * rb[7 + (v - 1)];
+                    sigI = ph.sig_iface;
+                } else if (bc == 2) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) { dQ[v] = qp[v] - ph.q_inf[v]; dV[v] = dQ[v]; }
+                    sigI = ph.sig_bc;
+                } else {
+                    double kn = sqrt(k2);
+                    double mn = (qp[1] * kap[0] + qp[2] * kap[1]) / kn;
+                    dQ[0] = 0.0; dV[0] = 0.0;
+                    dQ[1] = 2.0 * mn * kap[0] / kn; dV[1] = qp[1];
+                    dQ[2] = 2.0 * mn * kap[1] / kn; dV[2] = qp[2];
+                    dQ[3] = 0.0; dV[3] = qp[3] - qp[0] * ph.T_wall / gm1;
+                    sigI = ph.sig_bc;
+                    sig1 = ph.wall_visc * ph.mu * k2 / ph.Re;
+                    use_s2 = false;
+                }
+                double KdQ[4];
+                k_apply<2>(ph.gamma, qp, kap, sgn, dQ, KdQ);
+                double hs = 0.5 * sgn;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    double pen = -(sigI * KdQ[v] + sig1 * dV[v]) * ph.p0inv;
+                    if (use_s2) pen += hs * s2[v] * ph.p0inv;
+                    r[v] += pen;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) F[v * N + p] = r[v];
+    if (cb.m > 0) {
+        double hv[MAXH - 1][4];
+#pragma unroll
+        for (int j = 0; j < MAXH - 1; ++j)
+            if (j < cb.m - 1) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) hv[j][v] = cb.hist[j][v * N + p];
+            }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double a2 = q[v * N + p];
+#pragma unroll
+            for (int j = 0; j < MAXH - 1; ++j)
+                if (j < cb.m - 1) a2 = add_nc(a2, cb.c[j], hv[j][v]);
+            a2 = add_nc(a2, cb.c[cb.m - 1], r[v]);
+            cb.y_next[v * N + p] = a2;
         }
     }
 }
@@ -444,8 +751,8 @@ __global__ void __launch_bounds__(256) k_rhs(GridDev g, Phys ph, const double *_
 // when the donor grid is mid-step), donor viscous flux from the donor grid's
 // own SBP gradient, times the weight; a fixed butterfly over the S lanes of a
 // receiver sums the stencil.
-template <int DIM, int SBP>
-__global__ void __launch_bounds__(256) k_donor(DonorLaunch a)
+template <int DIM, int SBP, int CART>
+__global__ void __launch_bounds__(256) k_donor(DonorLink a)
 {
     constexpr int NV = DIM + 2;
     constexpr int RB = NV + DIM * (NV - 1);
@@ -453,34 +760,32 @@ __global__ void __launch_bounds__(256) k_donor(DonorLaunch a)
     int64_t k = lane / a.S;
     int e = (int)(lane % a.S);
     if (k >= a.nrecv) return;                 // whole groups of S lanes leave together
-    int rid = a.recv_list[k];
-    int64_t ent = (int64_t)rid * a.S + e;
-    int dg = a.ent_grid[ent];
-    int64_t p = a.ent_pt[ent];
-    double w = a.ent_w[ent];
-    const GridDev &g = a.grids[dg];
-    const StateSrc &s = a.src[dg];
-    const int64_t N = g.npts;
+    int64_t ent = k * a.S + e;
+    int64_t p = a.pts[ent];
+    double w = a.w[ent];
+    const int64_t N = a.g.npts;
+    const double *__restrict__ y = a.src.y;
+    const int mid = a.src.mid;
+    const int m = a.src.m;
     auto qload = [&](int64_t idx, double *o) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             int64_t el = v * N + idx;
-            double acc = s.y[el];
-            if (s.mid)
-                for (int j = 0; j < s.m; ++j) acc = add_nc(acc, s.beta[j], s.hist[j][el]);
+            double acc = y[el];
+            if (mid) {
+#pragma unroll
+                for (int j = 0; j < MAXH; ++j)
+                    if (j < m) acc = add_nc(acc, a.src.beta[j], a.src.hist[j][el]);
+            }
             o[v] = acc;
         }
     };
     double qp[NV];
     qload(p, qp);
     int ic[3];
-    coords(g, p, ic);
+    coords(a.g, p, ic);
     double gr[DIM + 1][DIM];
-    const double gm1 = a.ph.gamma - 1.0;
-    if (g.cartesian)
-        gradient<DIM, SBP, 1>(g, p, ic, gm1, qload, gr);
-    else
-        gradient<DIM, SBP, 0>(g, p, ic, gm1, qload, gr);
+    gradient<DIM, SBP, CART>(a.g, p, ic, a.ph.gamma - 1.0, qload, gr);
     double val[RB];
 #pragma unroll
     for (int v = 0; v < NV; ++v) val[v] = w * qp[v];
@@ -501,7 +806,7 @@ __global__ void __launch_bounds__(256) k_donor(DonorLaunch a)
         for (int t = 0; t < RB; ++t) val[t] += __shfl_xor(val[t], off, 64);
     }
     if (e == 0) {
-        double *o = a.out[a.recv_grid[rid]] + (int64_t)a.recv_row[rid] * RB;
+        double *o = a.out + (int64_t)(a.row0 + k) * RB;
 #pragma unroll
         for (int t = 0; t < RB; ++t) o[t] = val[t];
     }
@@ -513,7 +818,9 @@ __global__ void k_combine(int64_t n, const double *__restrict__ y, Combine cb)
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     double acc = y[e];
-    for (int j = 0; j < cb.m; ++j) acc = add_nc(acc, cb.c[j], cb.hist[j][e]);
+#pragma unroll
+    for (int j = 0; j < MAXH; ++j)
+        if (j < cb.m) acc = add_nc(acc, cb.c[j], cb.hist[j][e]);
     cb.y_next[e] = acc;
 }
 
@@ -665,6 +972,23 @@ hipError_t launch_rhs(const GridDev &g, const GridDev *, int sbp, const Phys &ph
     return hipGetLastError();
 }
 
+hipError_t launch_rhs_tile2d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *F,
+                             const Combine &cb, hipStream_t st)
+{
+    if (g.dim != 2) return hipErrorInvalidValue;
+    int ntx = (g.n[0] + 31) / 32, nty = (g.n[1] + 7) / 8;
+    dim3 grid(ntx * nty);
+    if (sbp == 21 && g.cartesian)
+        hipLaunchKernelGGL((k_rhs_tile2d<21, 1>), grid, dim3(256), 0, st, g, ph, q, F, cb, ntx, nty);
+    else if (sbp == 21)
+        hipLaunchKernelGGL((k_rhs_tile2d<21, 0>), grid, dim3(256), 0, st, g, ph, q, F, cb, ntx, nty);
+    else if (g.cartesian)
+        hipLaunchKernelGGL((k_rhs_tile2d<42, 1>), grid, dim3(256), 0, st, g, ph, q, F, cb, ntx, nty);
+    else
+        hipLaunchKernelGGL((k_rhs_tile2d<42, 0>), grid, dim3(256), 0, st, g, ph, q, F, cb, ntx, nty);
+    return hipGetLastError();
+}
+
 #define DISPATCH_GRAD(DIM, SBP, CART) \
     hipLaunchKernelGGL((k_grad<DIM, SBP, CART>), dim3(nblk(g.npts, 256)), dim3(256), 0, st, g, gm1, q, grad)
 
@@ -680,20 +1004,21 @@ hipError_t launch_grad(const GridDev &g, int sbp, double gm1, const double *q, d
     return hipGetLastError();
 }
 
-hipError_t launch_donor(const DonorLaunch &a, hipStream_t st)
+#define DISPATCH_DONOR(DIM, SBP, CART) \
+    hipLaunchKernelGGL((k_donor<DIM, SBP, CART>), dim3(nblk(lanes, 256)), dim3(256), 0, st, a)
+
+hipError_t launch_donor(const DonorLink &a, hipStream_t st)
 {
     if (a.nrecv == 0) return hipSuccess;
     int64_t lanes = a.nrecv * a.S;
-    if (a.dim == 2 && a.sbp == 21)
-        hipLaunchKernelGGL((k_donor<2, 21>), dim3(nblk(lanes, 256)), dim3(256), 0, st, a);
-    else if (a.dim == 2 && a.sbp == 42)
-        hipLaunchKernelGGL((k_donor<2, 42>), dim3(nblk(lanes, 256)), dim3(256), 0, st, a);
-    else if (a.dim == 3 && a.sbp == 21)
-        hipLaunchKernelGGL((k_donor<3, 21>), dim3(nblk(lanes, 256)), dim3(256), 0, st, a);
-    else if (a.dim == 3 && a.sbp == 42)
-        hipLaunchKernelGGL((k_donor<3, 42>), dim3(nblk(lanes, 256)), dim3(256), 0, st, a);
-    else
-        return hipErrorInvalidValue;
+    const GridDev &g = a.g;
+    if (g.dim == 2 && a.sbp == 21 && g.cartesian) DISPATCH_DONOR(2, 21, 1);
+    else if (g.dim == 2 && a.sbp == 21) DISPATCH_DONOR(2, 21, 0);
+    else if (g.dim == 2 && a.sbp == 42 && g.cartesian) DISPATCH_DONOR(2, 42, 1);
+    else if (g.dim == 2 && a.sbp == 42) DISPATCH_DONOR(2, 42, 0);
+    else if (g.dim == 3 && a.sbp == 21 && g.cartesian) DISPATCH_DONOR(3, 21, 1);
+    else if (g.dim == 3 && a.sbp == 42 && g.cartesian) DISPATCH_DONOR(3, 42, 1);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

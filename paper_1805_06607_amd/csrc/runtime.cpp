@@ -42,12 +42,17 @@ struct GridHost {
     double *rk[5] = {nullptr};
     int8_t *cls_d = nullptr;
     int32_t *recv_idx_d = nullptr;
-    int32_t *recv_list_d = nullptr;   // global receiver ids of this grid
     GridDev dev{};
     int head = 0;
 };
 
 }  // namespace
+
+struct Link {
+    int rg, dg;
+    int64_t first, n;     // global receiver range
+    int32_t row0;         // row of the first receiver in the receiving grid's buffer
+};
 
 struct mr_ctx {
     mr_params P{};
@@ -69,18 +74,15 @@ struct mr_ctx {
     std::vector<std::vector<std::vector<long double>>> alpha_mid;   // per grid, per jp
     std::vector<std::vector<double>> c_own;
     std::vector<std::vector<std::vector<double>>> beta;
-    std::vector<std::vector<int32_t>> pat;                           // per k = 1..rmax
-    std::vector<int32_t> all_recv;
-    int32_t *pat_d[64] = {nullptr};
-    int32_t *all_recv_d = nullptr;
-    int32_t *rgrid_d = nullptr, *rrow_d = nullptr, *ept_d = nullptr;
-    int8_t *egrid_d = nullptr;
+    std::vector<Link> links;
+    int32_t *ept_d = nullptr;
     double *ew_d = nullptr;
     GridDev *grids_d = nullptr;
     double *partial = nullptr;
     mrk::Phys ph{};
     // per-launch timing
     int tgrid = -1, tmax = 0, tcount = 0;
+    bool two_pass = false;    // 2D: use the two-kernel (gradient pass) right-hand side
     std::vector<hipEvent_t> ev;
 };
 
@@ -273,16 +275,10 @@ size_t layout(mr_ctx *c, char *base)
         size_t nr = g.recv_pts.size();
         g.recv_idx_d = nr ? cv.take<int32_t>((size_t)N) : nullptr;
         g.recv_buf = nr ? cv.take<double>(nr * (nv + g.dim * (nv - 1))) : nullptr;
-        g.recv_list_d = nr ? cv.take<int32_t>(nr) : nullptr;
     }
     size_t R = c->rgrid.size();
-    c->rgrid_d = cv.take<int32_t>(R + 1);
-    c->rrow_d = cv.take<int32_t>(R + 1);
-    c->egrid_d = cv.take<int8_t>(R * c->S + 1);
     c->ept_d = cv.take<int32_t>(R * c->S + 1);
     c->ew_d = cv.take<double>(R * c->S + 1);
-    c->all_recv_d = cv.take<int32_t>(R + 1);
-    for (int k = 1; k <= c->rmax; ++k) c->pat_d[k] = cv.take<int32_t>(c->pat[k].size() + 1);
     c->grids_d = cv.take<GridDev>(c->G.size());
     c->partial = cv.take<double>(1024);
     return cv.off + ALIGN;
@@ -295,28 +291,24 @@ double *slot(const mr_ctx *c, const GridHost &g, int j)   // j = 0 oldest .. m-1
     return g.hist + (size_t)s * (g.dim + 2) * g.npts;
 }
 
-int donor_launch(mr_ctx *c, const int32_t *list_d, int64_t nrecv, const mrk::StateSrc *src, double *const *out)
+// donor gather for every link whose receiving grid is selected (want[rg])
+int donor_links(mr_ctx *c, const bool *want, const mrk::StateSrc *src, double *const *out)
 {
-    if (nrecv == 0) return MR_OK;
-    mrk::DonorLaunch a{};
-    a.grids = c->grids_d;
-    for (size_t g = 0; g < c->G.size(); ++g) {
-        a.src[g] = src[g];
-        a.out[g] = out[g];
+    for (const Link &L : c->links) {
+        if (!want[L.rg] || L.n == 0) continue;
+        mrk::DonorLink a{};
+        a.g = c->G[L.dg].dev;
+        a.src = src[L.dg];
+        a.ph = c->ph;
+        a.out = out[L.rg];
+        a.row0 = L.row0;
+        a.pts = c->ept_d + L.first * c->S;
+        a.w = c->ew_d + L.first * c->S;
+        a.nrecv = L.n;
+        a.S = c->S;
+        a.sbp = c->P.sbp;
+        HIPCHK(c, mrk::launch_donor(a, c->st));
     }
-    a.recv_list = list_d;
-    a.recv_grid = c->rgrid_d;
-    a.recv_row = c->rrow_d;
-    a.ent_grid = c->egrid_d;
-    a.ent_pt = c->ept_d;
-    a.ent_w = c->ew_d;
-    a.nrecv = nrecv;
-    a.S = c->S;
-    a.dim = c->P.dim;
-    a.nv = c->P.dim + 2;
-    a.sbp = c->P.sbp;
-    a.ph = c->ph;
-    HIPCHK(c, mrk::launch_donor(a, c->st));
     return MR_OK;
 }
 
@@ -324,10 +316,14 @@ int donor_launch(mr_ctx *c, const int32_t *list_d, int64_t nrecv, const mrk::Sta
 int grid_rhs(mr_ctx *c, int gi, const double *q, double *F, const mrk::Combine &cb, bool timed)
 {
     GridHost &g = c->G[gi];
-    HIPCHK(c, mrk::launch_grad(g.dev, c->P.sbp, c->P.gamma - 1.0, q, g.grad, c->st));
     bool rec = timed && c->tgrid == gi && c->tcount < c->tmax;
     if (rec) HIPCHK(c, hipEventRecord(c->ev[2 * c->tcount], c->st));
-    HIPCHK(c, mrk::launch_rhs(g.dev, c->grids_d + gi, c->P.sbp, c->ph, q, g.grad, F, cb, c->st));
+    if (g.dim == 2 && !c->two_pass) {
+        HIPCHK(c, mrk::launch_rhs_tile2d(g.dev, c->P.sbp, c->ph, q, F, cb, c->st));
+    } else {
+        HIPCHK(c, mrk::launch_grad(g.dev, c->P.sbp, c->P.gamma - 1.0, q, g.grad, c->st));
+        HIPCHK(c, mrk::launch_rhs(g.dev, c->grids_d + gi, c->P.sbp, c->ph, q, g.grad, F, cb, c->st));
+    }
     if (rec) {
         HIPCHK(c, hipEventRecord(c->ev[2 * c->tcount + 1], c->st));
         c->tcount++;
@@ -345,7 +341,9 @@ int rhs_all(mr_ctx *c, const double *const *q, double *const *F)
         src[g].mid = 0;
         out[g] = c->G[g].recv_buf;
     }
-    int rc = donor_launch(c, c->all_recv_d, (int64_t)c->all_recv.size(), src, out);
+    bool all[mrk::MAXG];
+    for (int g = 0; g < mrk::MAXG; ++g) all[g] = true;
+    int rc = donor_links(c, all, src, out);
     if (rc) return rc;
     mrk::Combine none{};
     for (size_t g = 0; g < c->G.size(); ++g) {
@@ -446,6 +444,7 @@ int mr_set_overset(mr_ctx *c, int rg, int dg, int64_t n, int S, const int64_t *r
     c->S = S;
     GridHost &R = c->G[rg];
     GridHost &D = c->G[dg];
+    Link L{rg, dg, (int64_t)c->rgrid.size(), n, (int32_t)R.recv_pts.size()};
     for (int64_t r = 0; r < n; ++r) {
         int64_t p = recv_pt[r];
         if (p < 0 || p >= R.npts) return fail(c, MR_ERR_ARG, "receiver index out of range");
@@ -467,6 +466,7 @@ int mr_set_overset(mr_ctx *c, int rg, int dg, int64_t n, int S, const int64_t *r
             c->ew.push_back(w[r * S + e]);
         }
     }
+    if (n) c->links.push_back(L);
     return MR_OK;
 }
 
@@ -496,14 +496,6 @@ int mr_finalize(mr_ctx *c, size_t *bytes)
             if (!ab_alpha(n, m, (long double)jp / (long double)per, c->alpha_mid[g][jp]))
                 return fail(c, MR_ERR_SETUP, "AB coefficients");
     }
-    c->pat.assign(c->rmax + 1, {});
-    c->all_recv.clear();
-    for (int32_t r = 0; r < (int32_t)c->rgrid.size(); ++r) c->all_recv.push_back(r);
-    for (int k = 1; k <= c->rmax; ++k)
-        for (int32_t r = 0; r < (int32_t)c->rgrid.size(); ++r) {
-            int per = c->rmax / c->G[c->rgrid[r]].rate;
-            if (k % per == 0) c->pat[k].push_back(r);
-        }
     c->ws_bytes = layout(c, nullptr);
     c->finalized = true;
     *bytes = c->ws_bytes;
@@ -524,14 +516,9 @@ int mr_bind_workspace(mr_ctx *c, void *dev, size_t bytes)
     for (size_t gi = 0; gi < c->G.size(); ++gi) {
         GridHost &g = c->G[gi];
         HIPCHK(c, hipMemcpyAsync(g.cls_d, g.cls.data(), g.cls.size(), hipMemcpyHostToDevice, c->st));
-        if (!g.recv_pts.empty()) {
+        if (!g.recv_pts.empty())
             HIPCHK(c, hipMemcpyAsync(g.recv_idx_d, g.recv_idx.data(), g.recv_idx.size() * 4, hipMemcpyHostToDevice,
                                      c->st));
-            std::vector<int32_t> lst;
-            for (int32_t r = 0; r < (int32_t)c->rgrid.size(); ++r)
-                if (c->rgrid[r] == (int32_t)gi) lst.push_back(r);
-            HIPCHK(c, hipMemcpyAsync(g.recv_list_d, lst.data(), lst.size() * 4, hipMemcpyHostToDevice, c->st));
-        }
         GridDev &D = g.dev;
         D.dim = g.dim;
         D.nv = g.dim + 2;
@@ -556,16 +543,8 @@ int mr_bind_workspace(mr_ctx *c, void *dev, size_t bytes)
     }
     size_t R = c->rgrid.size();
     if (R) {
-        HIPCHK(c, hipMemcpyAsync(c->rgrid_d, c->rgrid.data(), R * 4, hipMemcpyHostToDevice, c->st));
-        HIPCHK(c, hipMemcpyAsync(c->rrow_d, c->rrow.data(), R * 4, hipMemcpyHostToDevice, c->st));
-        HIPCHK(c, hipMemcpyAsync(c->egrid_d, c->egrid.data(), R * c->S, hipMemcpyHostToDevice, c->st));
         HIPCHK(c, hipMemcpyAsync(c->ept_d, c->ept.data(), R * c->S * 4, hipMemcpyHostToDevice, c->st));
         HIPCHK(c, hipMemcpyAsync(c->ew_d, c->ew.data(), R * c->S * 8, hipMemcpyHostToDevice, c->st));
-        HIPCHK(c, hipMemcpyAsync(c->all_recv_d, c->all_recv.data(), R * 4, hipMemcpyHostToDevice, c->st));
-        for (int k = 1; k <= c->rmax; ++k)
-            if (!c->pat[k].empty())
-                HIPCHK(c, hipMemcpyAsync(c->pat_d[k], c->pat[k].data(), c->pat[k].size() * 4, hipMemcpyHostToDevice,
-                                         c->st));
     }
     HIPCHK(c, hipMemcpyAsync(c->grids_d, devs.data(), devs.size() * sizeof(GridDev), hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
@@ -614,12 +593,14 @@ int mr_receiver_data(mr_ctx *c, int g, const double *const *q, double *out)
     if (!c->bound) return fail(c, MR_ERR_STATE, "mr_receiver_data before mr_bind_workspace");
     mrk::StateSrc src[mrk::MAXG] = {};
     double *outs[mrk::MAXG] = {};
+    bool want[mrk::MAXG] = {};
     for (size_t k = 0; k < c->G.size(); ++k) {
         src[k].y = q[k];
         outs[k] = c->G[k].recv_buf;
     }
     outs[g] = out;
-    return donor_launch(c, c->G[g].recv_list_d, (int64_t)c->G[g].recv_pts.size(), src, outs);
+    want[g] = true;
+    return donor_links(c, want, src, outs);
 }
 
 int mr_timestep(mr_ctx *c, double *h, double *H)
@@ -744,7 +725,7 @@ int mr_mrab_macrostep(mr_ctx *c, int nsteps)
     int G = (int)c->G.size();
     for (int s = 0; s < nsteps; ++s) {
         for (int k = 1; k <= c->rmax; ++k) {
-            bool ends[mrk::MAXG];
+            bool ends[mrk::MAXG] = {};
             for (int g = 0; g < G; ++g) {
                 ends[g] = k % (c->rmax / c->G[g].rate) == 0;
                 if (ends[g]) c->G[g].cur ^= 1;   // the staged own step becomes current
@@ -765,7 +746,7 @@ int mr_mrab_macrostep(mr_ctx *c, int nsteps)
                     }
                 }
             }
-            int rc = donor_launch(c, c->pat_d[k], (int64_t)c->pat[k].size(), src, out);
+            int rc = donor_links(c, ends, src, out);
             if (rc) return rc;
             for (int g = 0; g < G; ++g) {
                 if (!ends[g]) continue;
