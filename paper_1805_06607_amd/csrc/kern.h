@@ -54,12 +54,21 @@ struct StateSrc {
 };
 
 // donor gather of one link (receivers of one grid taking data from one donor
-// grid): lanes (receiver k, entry e), k < nrecv, e < S
+// grid) for nj target times at once: lanes (slot j, receiver k, entry e).
+// Slot j reads the donor state y, or y + sum_h beta[j][h] hist[h] when
+// mid[j] (the donor grid's extrapolant, frozen between its own steps), and
+// writes the receiver rows out[j].
+constexpr int MAXJ = 8;
 struct DonorLink {
     GridDev g;                 // donor grid
-    StateSrc src;              // donor state (extrapolated when mid-step)
+    const double *y;
+    int m;
+    const double *hist[MAXH];
+    int nj;
+    int mid[MAXJ];
+    double beta[MAXJ][MAXH];
+    double *out[MAXJ];
     Phys ph;
-    double *out;               // receiving grid's receiver rows
     int32_t row0;              // row of the link's first receiver
     const int32_t *pts;        // nrecv x S donor points
     const double *w;           // nrecv x S weights

@@ -757,16 +757,30 @@ __global__ void __launch_bounds__(256) k_donor(DonorLink a)
     constexpr int NV = DIM + 2;
     constexpr int RB = NV + DIM * (NV - 1);
     int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t k = lane / a.S;
-    int e = (int)(lane % a.S);
-    if (k >= a.nrecv) return;                 // whole groups of S lanes leave together
-    int64_t ent = k * a.S + e;
-    int64_t p = a.pts[ent];
-    double w = a.w[ent];
+    const int64_t per_slot = a.nrecv * a.S;
+    const int j = (int)(lane / per_slot);
+    if (j >= a.nj) return;                    // whole groups of S lanes leave together
+    const int64_t rem = lane - (int64_t)j * per_slot;
+    const int64_t k = rem / a.S;
+    const int e = (int)(rem % a.S);
+    const int64_t ent = k * a.S + e;
+    const int64_t p = a.pts[ent];
+    const double w = a.w[ent];
     const int64_t N = a.g.npts;
-    const double *__restrict__ y = a.src.y;
-    const int mid = a.src.mid;
-    const int m = a.src.m;
+    const double *__restrict__ y = a.y;
+    const int m = a.m;
+    // the slot's extrapolation row and output, selected with constant indices
+    int mid = 0;
+    double bj[MAXH];
+    double *outp = nullptr;
+#pragma unroll
+    for (int jj = 0; jj < MAXJ; ++jj)
+        if (jj == j) {
+            mid = a.mid[jj];
+            outp = a.out[jj];
+#pragma unroll
+            for (int hh = 0; hh < MAXH; ++hh) bj[hh] = a.beta[jj][hh];
+        }
     auto qload = [&](int64_t idx, double *o) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -774,8 +788,8 @@ __global__ void __launch_bounds__(256) k_donor(DonorLink a)
             double acc = y[el];
             if (mid) {
 #pragma unroll
-                for (int j = 0; j < MAXH; ++j)
-                    if (j < m) acc = add_nc(acc, a.src.beta[j], a.src.hist[j][el]);
+                for (int hh = 0; hh < MAXH; ++hh)
+                    if (hh < m) acc = add_nc(acc, bj[hh], a.hist[hh][el]);
             }
             o[v] = acc;
         }
@@ -797,16 +811,16 @@ __global__ void __launch_bounds__(256) k_donor(DonorLink a)
         double Fv[DIM][DIM + 1];
         viscous_flux<DIM>(a.ph, u, gr, Fv);
 #pragma unroll
-        for (int j = 0; j < DIM; ++j)
+        for (int d = 0; d < DIM; ++d)
 #pragma unroll
-            for (int v = 1; v < NV; ++v) val[NV + j * (NV - 1) + (v - 1)] = w * Fv[j][v - 1];
+            for (int v = 1; v < NV; ++v) val[NV + d * (NV - 1) + (v - 1)] = w * Fv[d][v - 1];
     }
     for (int off = 1; off < a.S; off <<= 1) {
 #pragma unroll
         for (int t = 0; t < RB; ++t) val[t] += __shfl_xor(val[t], off, 64);
     }
     if (e == 0) {
-        double *o = a.out + (int64_t)(a.row0 + k) * RB;
+        double *o = outp + (int64_t)(a.row0 + k) * RB;
 #pragma unroll
         for (int t = 0; t < RB; ++t) o[t] = val[t];
     }
@@ -1009,8 +1023,8 @@ hipError_t launch_grad(const GridDev &g, int sbp, double gm1, const double *q, d
 
 hipError_t launch_donor(const DonorLink &a, hipStream_t st)
 {
-    if (a.nrecv == 0) return hipSuccess;
-    int64_t lanes = a.nrecv * a.S;
+    if (a.nrecv == 0 || a.nj == 0) return hipSuccess;
+    int64_t lanes = a.nrecv * a.S * a.nj;
     const GridDev &g = a.g;
     if (g.dim == 2 && a.sbp == 21 && g.cartesian) DISPATCH_DONOR(2, 21, 1);
     else if (g.dim == 2 && a.sbp == 21) DISPATCH_DONOR(2, 21, 0);

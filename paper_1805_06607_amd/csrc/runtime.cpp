@@ -274,7 +274,7 @@ size_t layout(mr_ctx *c, char *base)
         g.coords_d = g.kind == MR_CURVILINEAR ? cv.take<double>((size_t)g.dim * N) : nullptr;
         size_t nr = g.recv_pts.size();
         g.recv_idx_d = nr ? cv.take<int32_t>((size_t)N) : nullptr;
-        g.recv_buf = nr ? cv.take<double>(nr * (nv + g.dim * (nv - 1))) : nullptr;
+        g.recv_buf = nr ? cv.take<double>(nr * (nv + g.dim * (nv - 1)) * c->rmax) : nullptr;
     }
     size_t R = c->rgrid.size();
     c->ept_d = cv.take<int32_t>(R * c->S + 1);
@@ -291,38 +291,79 @@ double *slot(const mr_ctx *c, const GridHost &g, int j)   // j = 0 oldest .. m-1
     return g.hist + (size_t)s * (g.dim + 2) * g.npts;
 }
 
-// donor gather for every link whose receiving grid is selected (want[rg])
-int donor_links(mr_ctx *c, const bool *want, const mrk::StateSrc *src, double *const *out)
+// receiver rows of grid g for micro-time k (1..rmax)
+double *recv_slice(const mr_ctx *c, const GridHost &g, int k)
 {
-    for (const Link &L : c->links) {
-        if (!want[L.rg] || L.n == 0) continue;
-        mrk::DonorLink a{};
-        a.g = c->G[L.dg].dev;
-        a.src = src[L.dg];
-        a.ph = c->ph;
-        a.out = out[L.rg];
-        a.row0 = L.row0;
-        a.pts = c->ept_d + L.first * c->S;
-        a.w = c->ew_d + L.first * c->S;
-        a.nrecv = L.n;
-        a.S = c->S;
-        a.sbp = c->P.sbp;
-        HIPCHK(c, mrk::launch_donor(a, c->st));
+    if (!g.recv_buf) return nullptr;
+    size_t rb = (size_t)(g.dim + 2) + (size_t)g.dim * (g.dim + 1);
+    return g.recv_buf + (size_t)(k - 1) * g.recv_pts.size() * rb;
+}
+
+mrk::DonorLink link_base(const mr_ctx *c, const Link &L)
+{
+    mrk::DonorLink a{};
+    a.g = c->G[L.dg].dev;
+    a.ph = c->ph;
+    a.row0 = L.row0;
+    a.pts = c->ept_d + L.first * c->S;
+    a.w = c->ew_d + L.first * c->S;
+    a.nrecv = L.n;
+    a.S = c->S;
+    a.sbp = c->P.sbp;
+    return a;
+}
+
+// donor data from the donor grid's state y into out (one target time)
+int link_current(mr_ctx *c, const Link &L, const double *y, double *out)
+{
+    mrk::DonorLink a = link_base(c, L);
+    a.y = y;
+    a.nj = 1;
+    a.mid[0] = 0;
+    a.out[0] = out;
+    HIPCHK(c, mrk::launch_donor(a, c->st));
+    return MR_OK;
+}
+
+// right after donor grid d evaluated at micro-time k: donor data for every
+// later micro-time k' < k + per_d at which the receiving grid evaluates and d
+// is mid-step, from d's extrapolant (frozen until d's next step)
+int link_future(mr_ctx *c, const Link &L, int k)
+{
+    const GridHost &D = c->G[L.dg];
+    const GridHost &R = c->G[L.rg];
+    int per_d = c->rmax / D.rate, per_g = c->rmax / R.rate;
+    mrk::DonorLink a = link_base(c, L);
+    a.y = D.y[D.cur];
+    a.m = c->P.hist_len;
+    for (int j = 0; j < a.m; ++j) a.hist[j] = slot(c, D, j);
+    a.nj = 0;
+    for (int jp = 1; jp < per_d; ++jp) {
+        int kp = k + jp;
+        if (kp > c->rmax) kp -= c->rmax;
+        if (kp % per_g) continue;
+        a.mid[a.nj] = 1;
+        for (int j = 0; j < a.m; ++j) a.beta[a.nj][j] = c->beta[L.dg][jp][j];
+        a.out[a.nj] = recv_slice(c, R, kp);
+        a.nj++;
     }
+    if (a.nj) HIPCHK(c, mrk::launch_donor(a, c->st));
     return MR_OK;
 }
 
 // right-hand side of one grid from state q into F (+ optional fused combine)
-int grid_rhs(mr_ctx *c, int gi, const double *q, double *F, const mrk::Combine &cb, bool timed)
+int grid_rhs(mr_ctx *c, int gi, const double *q, double *F, const mrk::Combine &cb, bool timed, int k)
 {
     GridHost &g = c->G[gi];
+    GridDev dev = g.dev;
+    dev.recv = recv_slice(c, g, k);
     bool rec = timed && c->tgrid == gi && c->tcount < c->tmax;
     if (rec) HIPCHK(c, hipEventRecord(c->ev[2 * c->tcount], c->st));
     if (g.dim == 2 && !c->two_pass) {
-        HIPCHK(c, mrk::launch_rhs_tile2d(g.dev, c->P.sbp, c->ph, q, F, cb, c->st));
+        HIPCHK(c, mrk::launch_rhs_tile2d(dev, c->P.sbp, c->ph, q, F, cb, c->st));
     } else {
-        HIPCHK(c, mrk::launch_grad(g.dev, c->P.sbp, c->P.gamma - 1.0, q, g.grad, c->st));
-        HIPCHK(c, mrk::launch_rhs(g.dev, c->grids_d + gi, c->P.sbp, c->ph, q, g.grad, F, cb, c->st));
+        HIPCHK(c, mrk::launch_grad(dev, c->P.sbp, c->P.gamma - 1.0, q, g.grad, c->st));
+        HIPCHK(c, mrk::launch_rhs(dev, c->grids_d + gi, c->P.sbp, c->ph, q, g.grad, F, cb, c->st));
     }
     if (rec) {
         HIPCHK(c, hipEventRecord(c->ev[2 * c->tcount + 1], c->st));
@@ -331,23 +372,16 @@ int grid_rhs(mr_ctx *c, int gi, const double *q, double *F, const mrk::Combine &
     return MR_OK;
 }
 
-// coupled right-hand side of all grids
+// coupled right-hand side of all grids at one time
 int rhs_all(mr_ctx *c, const double *const *q, double *const *F)
 {
-    mrk::StateSrc src[mrk::MAXG] = {};
-    double *out[mrk::MAXG] = {};
-    for (size_t g = 0; g < c->G.size(); ++g) {
-        src[g].y = q[g];
-        src[g].mid = 0;
-        out[g] = c->G[g].recv_buf;
+    for (const Link &L : c->links) {
+        int rc = link_current(c, L, q[L.dg], recv_slice(c, c->G[L.rg], 1));
+        if (rc) return rc;
     }
-    bool all[mrk::MAXG];
-    for (int g = 0; g < mrk::MAXG; ++g) all[g] = true;
-    int rc = donor_links(c, all, src, out);
-    if (rc) return rc;
     mrk::Combine none{};
     for (size_t g = 0; g < c->G.size(); ++g) {
-        rc = grid_rhs(c, (int)g, q[g], F[g], none, false);
+        int rc = grid_rhs(c, (int)g, q[g], F[g], none, false, 1);
         if (rc) return rc;
     }
     return MR_OK;
@@ -591,16 +625,13 @@ int mr_receiver_data(mr_ctx *c, int g, const double *const *q, double *out)
 {
     if (!c || !q || !out || g < 0 || g >= (int)c->G.size()) return MR_ERR_ARG;
     if (!c->bound) return fail(c, MR_ERR_STATE, "mr_receiver_data before mr_bind_workspace");
-    mrk::StateSrc src[mrk::MAXG] = {};
-    double *outs[mrk::MAXG] = {};
-    bool want[mrk::MAXG] = {};
-    for (size_t k = 0; k < c->G.size(); ++k) {
-        src[k].y = q[k];
-        outs[k] = c->G[k].recv_buf;
+    for (const Link &L : c->links) {
+        if (L.rg != g) continue;
+        if (!q[L.dg]) return fail(c, MR_ERR_ARG, "null donor state");
+        int rc = link_current(c, L, q[L.dg], out);
+        if (rc) return rc;
     }
-    outs[g] = out;
-    want[g] = true;
-    return donor_links(c, want, src, outs);
+    return MR_OK;
 }
 
 int mr_timestep(mr_ctx *c, double *h, double *H)
@@ -711,6 +742,12 @@ int mr_mrab_start(mr_ctx *c, double t0)
         cb.y_next = Gh.y[1 - Gh.cur];
         HIPCHK(c, mrk::launch_combine(nelem(Gh), Gh.y[Gh.cur], cb, c->st));
     }
+    // every grid has just evaluated: donor data of the first macrostep's
+    // mid-step times
+    for (const Link &L : c->links) {
+        int rc = link_future(c, L, c->rmax);
+        if (rc) return rc;
+    }
     c->t = t0 + nsteps * d;
     c->nmacro = 0;
     c->started = true;
@@ -730,24 +767,14 @@ int mr_mrab_macrostep(mr_ctx *c, int nsteps)
                 ends[g] = k % (c->rmax / c->G[g].rate) == 0;
                 if (ends[g]) c->G[g].cur ^= 1;   // the staged own step becomes current
             }
-            mrk::StateSrc src[mrk::MAXG] = {};
-            double *out[mrk::MAXG] = {};
-            for (int g = 0; g < G; ++g) {
-                GridHost &Gh = c->G[g];
-                src[g].y = Gh.y[Gh.cur];
-                out[g] = Gh.recv_buf;
-                if (!ends[g]) {
-                    int per = c->rmax / Gh.rate;
-                    src[g].mid = 1;
-                    src[g].m = m;
-                    for (int j = 0; j < m; ++j) {
-                        src[g].beta[j] = c->beta[g][k % per][j];
-                        src[g].hist[j] = slot(c, Gh, j);
-                    }
-                }
+            // donor data from donors at their own step; mid-step donor data
+            // was gathered right after the donor grid's last evaluation
+            for (const Link &L : c->links) {
+                if (!ends[L.rg] || !ends[L.dg]) continue;
+                const GridHost &D = c->G[L.dg];
+                int rc = link_current(c, L, D.y[D.cur], recv_slice(c, c->G[L.rg], k));
+                if (rc) return rc;
             }
-            int rc = donor_links(c, ends, src, out);
-            if (rc) return rc;
             for (int g = 0; g < G; ++g) {
                 if (!ends[g]) continue;
                 GridHost &Gh = c->G[g];
@@ -757,9 +784,14 @@ int mr_mrab_macrostep(mr_ctx *c, int nsteps)
                 for (int j = 0; j < m; ++j) cb.c[j] = c->c_own[g][j];
                 cb.y_next = Gh.y[1 - Gh.cur];
                 double *Fnew = slot(c, Gh, 0);      // the oldest slot is overwritten
-                rc = grid_rhs(c, g, Gh.y[Gh.cur], Fnew, cb, true);
+                int rc = grid_rhs(c, g, Gh.y[Gh.cur], Fnew, cb, true, k);
                 if (rc) return rc;
                 Gh.head = (Gh.head + 1) % m;
+            }
+            for (const Link &L : c->links) {
+                if (!ends[L.dg] || c->G[L.dg].rate == c->rmax) continue;
+                int rc = link_future(c, L, k);
+                if (rc) return rc;
             }
         }
         c->t += c->H;

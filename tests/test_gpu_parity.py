@@ -169,3 +169,16 @@ def test_determinism_bitwise(torch):
         outs.append([s.state(g).clone() for g in range(2)])
     for g in range(2):
         assert torch.equal(outs[0][g], outs[1][g])
+
+
+def test_mrab_parity_full_size_cylinder(torch):
+    """The benchmark workload itself (512^2 background + 256x128 O-mesh, AB4,
+    ratio 4): 100 macrosteps, GPU vs oracle."""
+    wl = workloads.cylinder()
+    _say("mrab parity full-size cylinder")
+    orc, mr, sysg = _run_both(wl, 100)
+    for g in range(len(wl.grids)):
+        act = orc.grids[g].iblank.astype(bool)
+        e = rel_l2(_np(sysg.state(g)), mr.y[g], act)
+        _say("cylinder full", g, e)
+        assert np.all(e <= 1e-10), (g, e)
