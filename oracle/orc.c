@@ -341,6 +341,73 @@ int orc_kmatrix(int dim, double gamma, const double *qp, const double *nvec, int
     return 0;
 }
 
+/* SAT penalty of the run end (direction m, side sgn: +1 run start, -1 run
+ * end) at point p with boundary flag bc: pen (nv values) */
+static int sat_term(const OrcGrid *g, int64_t p, int m, int bc, int sgn, const double *qp, double Fvp[3][5],
+                    const double *recv, int RB, double *pen)
+{
+    int dim = g->dim, nv = g->nv;
+    double kap[3], k2 = 0.0;
+    for (int j = 0; j < dim; ++j) { kap[j] = Jac(g, p) * Mmj(g, p, m, j); k2 = k2 + kap[j] * kap[j]; }
+    double qt[5], qv[5];      /* targets of the K term and of the sigma_1 term */
+    double Fvk[5], Fvkh[5];
+    for (int v = 0; v < nv; ++v) {
+        double s = 0.0;
+        for (int j = 0; j < dim; ++j) s = s + kap[j] * Fvp[j][v];
+        Fvk[v] = s;
+        Fvkh[v] = 0.0;
+    }
+    double sigI, sig1 = g->mu * k2 / (2.0 * g->Re);
+    int use_s2 = 1;
+    if (bc == BC_INTERFACE) {
+        int ri = g->recv_idx[p];
+        if (ri < 0) return -1;
+        const double *rb = recv + (int64_t)ri * RB;
+        for (int v = 0; v < nv; ++v) qt[v] = rb[v];
+        for (int v = 1; v < nv; ++v) {
+            double s = 0.0;
+            for (int j = 0; j < dim; ++j) s = s + kap[j] * rb[nv + j * (nv - 1) + (v - 1)];
+            Fvkh[v] = s;
+        }
+        for (int v = 0; v < nv; ++v) qv[v] = qt[v];
+        sigI = g->sig_iface;
+    } else if (bc == BC_FARFIELD) {
+        for (int v = 0; v < nv; ++v) qt[v] = g->q_inf[v];
+        for (int v = 0; v < nv; ++v) qv[v] = qt[v];
+        sigI = g->sig_bc;
+    } else if (bc == BC_WALL) {
+        /* inviscid part: the point's own state with the normal momentum
+         * reflected (characteristic no-penetration); viscous part: rest at the
+         * wall temperature */
+        double mn = 0.0, kn = sqrt(k2);
+        for (int i = 0; i < dim; ++i) mn = mn + qp[1 + i] * kap[i] / kn;
+        qt[0] = qp[0];
+        for (int i = 0; i < dim; ++i) qt[1 + i] = qp[1 + i] - 2.0 * mn * kap[i] / kn;
+        qt[dim + 1] = qp[dim + 1];
+        qv[0] = qp[0];
+        for (int i = 0; i < dim; ++i) qv[1 + i] = 0.0;
+        qv[dim + 1] = qp[0] * g->T_wall / (g->gamma - 1.0);
+        sigI = g->sig_bc;
+        sig1 = g->wall_visc * g->mu * k2 / g->Re;
+        use_s2 = 0;
+    } else {
+        return -1;
+    }
+    double K[25];
+    if (orc_kmatrix(dim, g->gamma, qp, kap, sgn, K) != 0) return -1;
+    double dQ[5], dV[5];
+    for (int v = 0; v < nv; ++v) { dQ[v] = qp[v] - qt[v]; dV[v] = qp[v] - qv[v]; }
+    double s2 = 0.5 * sgn;
+    for (int v = 0; v < nv; ++v) {
+        double kd = 0.0;
+        for (int c2 = 0; c2 < nv; ++c2) kd = kd + K[v * nv + c2] * dQ[c2];
+        double pv = -(sigI * kd + sig1 * dV[v]) / g->p0;
+        if (use_s2) pv = pv + s2 * (Fvk[v] - Fvkh[v]) / g->p0;
+        pen[v] = pv;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------- RHS */
 static double *alloc(int64_t n) { return (double *)calloc((size_t)n, sizeof(double)); }
 
@@ -400,65 +467,11 @@ int orc_rhs(const OrcGrid *g, const double *q, const double *recv, double *dqdt)
                 if (!at_end) continue;
                 int bc = side == 0 ? g->bclo[m][p] : g->bchi[m][p];
                 int sgn = side == 0 ? +1 : -1;      /* '+' face at the run start */
-                double kap[3], k2 = 0.0;
-                for (int j = 0; j < dim; ++j) { kap[j] = Jac(g, p) * Mmj(g, p, m, j); k2 = k2 + kap[j] * kap[j]; }
-                double qt[5], qv[5];      /* targets of the K term and of the sigma_1 term */
-                double Fvk[5], Fvkh[5];
-                for (int v = 0; v < nv; ++v) {
-                    double s = 0.0;
-                    for (int j = 0; j < dim; ++j) s = s + kap[j] * Fvis[((int64_t)j * nv + v) * N + p];
-                    Fvk[v] = s;
-                    Fvkh[v] = 0.0;
-                }
-                double sigI, sig1 = g->mu * k2 / (2.0 * g->Re);
-                int use_s2 = 1;
-                if (bc == BC_INTERFACE) {
-                    int ri = g->recv_idx[p];
-                    if (ri < 0) { err = 1; continue; }
-                    const double *rb = recv + (int64_t)ri * RB;
-                    for (int v = 0; v < nv; ++v) qt[v] = rb[v];
-                    for (int v = 1; v < nv; ++v) {
-                        double s = 0.0;
-                        for (int j = 0; j < dim; ++j) s = s + kap[j] * rb[nv + j * (nv - 1) + (v - 1)];
-                        Fvkh[v] = s;
-                    }
-                    for (int v = 0; v < nv; ++v) qv[v] = qt[v];
-                    sigI = g->sig_iface;
-                } else if (bc == BC_FARFIELD) {
-                    for (int v = 0; v < nv; ++v) qt[v] = g->q_inf[v];
-                    for (int v = 0; v < nv; ++v) qv[v] = qt[v];
-                    sigI = g->sig_bc;
-                } else if (bc == BC_WALL) {
-                    /* inviscid part: the point's own state with the normal
-                     * momentum reflected (characteristic no-penetration);
-                     * viscous part: rest at the wall temperature */
-                    double mn = 0.0, kn = sqrt(k2);
-                    for (int i = 0; i < dim; ++i) mn = mn + qp[1 + i] * kap[i] / kn;
-                    qt[0] = qp[0];
-                    for (int i = 0; i < dim; ++i) qt[1 + i] = qp[1 + i] - 2.0 * mn * kap[i] / kn;
-                    qt[dim + 1] = qp[dim + 1];
-                    qv[0] = qp[0];
-                    for (int i = 0; i < dim; ++i) qv[1 + i] = 0.0;
-                    qv[dim + 1] = qp[0] * g->T_wall / (g->gamma - 1.0);
-                    sigI = g->sig_bc;
-                    sig1 = g->wall_visc * g->mu * k2 / g->Re;
-                    use_s2 = 0;
-                } else {
-                    err = 1;
-                    continue;
-                }
-                double K[25];
-                if (orc_kmatrix(dim, g->gamma, qp, kap, sgn, K) != 0) { err = 1; continue; }
-                double dQ[5], dV[5];
-                for (int v = 0; v < nv; ++v) { dQ[v] = qp[v] - qt[v]; dV[v] = qp[v] - qv[v]; }
-                double s2 = 0.5 * sgn;
-                for (int v = 0; v < nv; ++v) {
-                    double kd = 0.0;
-                    for (int c2 = 0; c2 < nv; ++c2) kd = kd + K[v * nv + c2] * dQ[c2];
-                    double pen = -(sigI * kd + sig1 * dV[v]) / g->p0;
-                    if (use_s2) pen = pen + s2 * (Fvk[v] - Fvkh[v]) / g->p0;
-                    r[v] = r[v] + pen;
-                }
+                double pen[5], Fvp[3][5];
+                for (int j = 0; j < dim; ++j)
+                    for (int v = 0; v < nv; ++v) Fvp[j][v] = Fvis[((int64_t)j * nv + v) * N + p];
+                if (sat_term(g, p, m, bc, sgn, qp, Fvp, recv, RB, pen) != 0) { err = 1; continue; }
+                for (int v = 0; v < nv; ++v) r[v] = r[v] + pen[v];
             }
         }
         for (int v = 0; v < nv; ++v) dqdt[(int64_t)v * N + p] = r[v];
@@ -531,6 +544,85 @@ int orc_deriv(const OrcGrid *g, const double *f, int d, double *out)
     for (int64_t p = 0; p < g->npts; ++p)
         out[p] = active(g, p) ? dapply(g, f, p, d) : 0.0;
     return 0;
+}
+
+/* right-hand side at listed points only (same definition as orc_rhs: the
+ * contravariant fluxes at each point's stencil columns are evaluated where
+ * needed instead of on the whole grid); for sampled checks of large grids */
+int orc_rhs_points(const OrcGrid *g, const double *q, const double *recv, int64_t np, const int64_t *pts,
+                   double *out)
+{
+    int dim = g->dim, nv = g->nv;
+    int64_t N = g->npts;
+    int RB = nv + dim * (nv - 1);
+    Work w;
+    w.rho = alloc(N); w.p = alloc(N); w.T = alloc(N);
+    for (int i = 0; i < 3; ++i) w.u[i] = alloc(N);
+    if (!w.rho || !w.p || !w.T || !w.u[2]) return -1;
+    primitives(g, q, &w);
+    int err = 0;
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < np; ++r) {
+        int64_t p = pts[r];
+        double *o = out + r * nv;
+        if (p < 0 || p >= N) { err = 1; continue; }
+        if (!active(g, p)) { for (int v = 0; v < nv; ++v) o[v] = 0.0; continue; }
+        /* contravariant flux of direction m at point s */
+        double res[5] = {0, 0, 0, 0, 0};
+        for (int m = 0; m < dim; ++m) {
+            int L = g->rlen[m][p], i = g->pos[m][p];
+            int cols[6], nc = 0;
+            double cf[6];
+            if (L != 0 && i < g->nb) {
+                for (int c2 = 0; c2 < g->cw; ++c2) { cols[nc] = c2 - i; cf[nc++] = g->dclo[i][c2]; }
+            } else if (L != 0 && i >= L - g->nb) {
+                int rr = L - 1 - i;
+                for (int c2 = 0; c2 < g->cw; ++c2) { cols[nc] = rr - c2; cf[nc++] = -g->dclo[rr][c2]; }
+            } else {
+                for (int o2 = -g->hw; o2 <= g->hw; ++o2) {
+                    if (o2 == 0) continue;
+                    cols[nc] = o2; cf[nc++] = g->dint[o2 + 2];
+                }
+            }
+            double sum[5] = {0, 0, 0, 0, 0};
+            for (int t = 0; t < nc; ++t) {
+                int64_t s = nbr(g, p, m, cols[t]);
+                double gr[4][3], Fv[3][5], Fi[3][5];
+                gradient_at(g, &w, s, gr);
+                viscous_flux(g, &w, s, gr, Fv);
+                inviscid_flux(g, q, &w, s, Fi);
+                for (int v = 0; v < nv; ++v) {
+                    double fh = 0.0;
+                    for (int j = 0; j < dim; ++j) fh = fh + Mmj(g, s, m, j) * (Fi[j][v] - Fv[j][v]);
+                    sum[v] = sum[v] + cf[t] * fh;
+                }
+            }
+            for (int v = 0; v < nv; ++v) res[v] = res[v] + sum[v];
+        }
+        for (int v = 0; v < nv; ++v) o[v] = -Jac(g, p) * res[v];
+        /* SAT terms: reuse the whole-grid routine's definition on a one-point basis */
+        double gr[4][3], Fvp[3][5];
+        gradient_at(g, &w, p, gr);
+        viscous_flux(g, &w, p, gr, Fvp);
+        double qp[5];
+        for (int v = 0; v < nv; ++v) qp[v] = q[(int64_t)v * N + p];
+        for (int m = 0; m < dim; ++m) {
+            int L = g->rlen[m][p];
+            if (L <= 0) continue;
+            for (int side = 0; side < 2; ++side) {
+                int at_end = side == 0 ? (g->pos[m][p] == 0) : (g->pos[m][p] == L - 1);
+                if (!at_end) continue;
+                int bc = side == 0 ? g->bclo[m][p] : g->bchi[m][p];
+                int sgn = side == 0 ? +1 : -1;
+                double pen[5];
+                if (sat_term(g, p, m, bc, sgn, qp, Fvp, recv, RB, pen) != 0) { err = 1; continue; }
+                for (int v = 0; v < nv; ++v) o[v] = o[v] + pen[v];
+            }
+        }
+    }
+    free(w.rho); free(w.p); free(w.T);
+    for (int i = 0; i < 3; ++i) free(w.u[i]);
+    return err ? -2 : 0;
 }
 
 int orc_abi_version(void) { return 1; }

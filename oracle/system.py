@@ -41,6 +41,9 @@ def load_library():
         lib.orc_metrics2d.argtypes = [P, POINTER(c_double), POINTER(c_double), POINTER(c_double),
                                       POINTER(c_double), POINTER(c_double)]
         lib.orc_deriv.argtypes = [P, POINTER(c_double), c_int, POINTER(c_double)]
+        lib.orc_rhs_points.argtypes = [P, POINTER(c_double), POINTER(c_double), c_int64, POINTER(c_int64),
+                                       POINTER(c_double)]
+        lib.orc_rhs_points.restype = c_int
         lib.orc_kmatrix.argtypes = [c_int, c_double, POINTER(c_double), POINTER(c_double), c_int,
                                     POINTER(c_double)]
         for f in (lib.orc_rhs, lib.orc_donor, lib.orc_dt, lib.orc_metrics2d, lib.orc_kmatrix,
@@ -229,6 +232,20 @@ class OracleSystem:
         rc = self.lib.orc_rhs(ctypes.byref(self.grids[g].struct), _dp(qc), _dp(rb), _dp(out))
         if rc != 0:
             raise RuntimeError(f"orc_rhs failed ({rc})")
+        return out
+
+    def rhs_points(self, g: int, q: np.ndarray, recv: np.ndarray, pts) -> np.ndarray:
+        """Right-hand side of grid g at the listed points only, (len(pts), nv)."""
+        qc = np.ascontiguousarray(q, dtype=np.float64).reshape(self.nv, -1)
+        rb = np.ascontiguousarray(recv, dtype=np.float64)
+        if rb.size == 0:
+            rb = np.zeros((1, self.RB))
+        pts = np.ascontiguousarray(pts, dtype=np.int64)
+        out = np.zeros((len(pts), self.nv))
+        rc = self.lib.orc_rhs_points(ctypes.byref(self.grids[g].struct), _dp(qc), _dp(rb), len(pts),
+                                     pts.ctypes.data_as(POINTER(c_int64)), _dp(out))
+        if rc != 0:
+            raise RuntimeError(f"orc_rhs_points failed ({rc})")
         return out
 
     def rhs(self, states: List[np.ndarray], which=None) -> Dict[int, np.ndarray]:

@@ -1,0 +1,84 @@
+"""GPU parity on the 3D three-level case (periodic background, two patches at
+half spacing, an inner patch at quarter spacing; rates 1, 2, 2, 4; SBP 4-2,
+cubic donors, AB3) against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import rel_l2, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def small():
+    return workloads.tgv3d(nbg=48, npatch=24, ninner=16)
+
+
+def test_rhs_parity_3d(torch):
+    from oracle import OracleSystem
+    from paper_1805_06607_amd.system import System
+    wl = small()
+    states = workloads.random_state_like(wl, seed=9, amp=0.02)
+    orc = OracleSystem(wl)
+    want = orc.rhs(states)
+    got = System(wl).rhs(states)
+    for g in range(len(wl.grids)):
+        act = orc.grids[g].iblank.astype(bool)
+        e = rel_l2(_np(got[g]), want[g], act)
+        _say("3d rhs", g, e)
+        assert np.all(e <= 1e-12), (g, e)
+
+
+def test_receiver_data_parity_3d(torch):
+    from oracle import OracleSystem
+    from paper_1805_06607_amd.system import System
+    wl = small()
+    states = workloads.random_state_like(wl, seed=4, amp=0.02)
+    orc = OracleSystem(wl)
+    sysg = System(wl)
+    for g in range(len(wl.grids)):
+        want = orc.receiver_data(g, states)
+        got = _np(sysg.receiver_data(g, states))
+        e = rel_l2(got.T, want.T)
+        _say("3d receiver data", g, e)
+        assert np.all(e <= 1e-13), e
+
+
+def test_mrab_parity_3d_100_macrosteps(torch):
+    from oracle import OracleSystem
+    from paper_1805_06607_amd.system import System
+    wl = small()
+    orc = OracleSystem(wl)
+    h, H = orc.timestep()
+    wl.params["dt_fixed"] = H
+    mr = orc.integrator(H)
+    mr.bootstrap(wl.q0)
+    sysg = System(wl)
+    sysg.timestep()
+    sysg.start(0.0)
+    sysg.macrostep(100)
+    for k in range(100):
+        mr.macrostep()
+        if k % 20 == 19:
+            _say("oracle macrostep", k + 1)
+    for g in range(len(wl.grids)):
+        act = orc.grids[g].iblank.astype(bool)
+        e = rel_l2(_np(sysg.state(g)), mr.y[g], act)
+        _say("3d mrab", g, e)
+        assert np.all(e <= 1e-10), (g, e)
