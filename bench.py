@@ -223,11 +223,22 @@ def main():
     ap.add_argument("--ee-macrosteps", type=int, default=200)
     ap.add_argument("--ee-spinup", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the method's work here has no multi-GPU path "
               "(see the sharding design notes); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy_mib:
+        import torch
+        n = args.calibrate_copy_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        c = torch.empty_like(a)
+        c.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calibrate_copy_mib} MiB read + {args.calibrate_copy_mib} MiB written")
+        del a, c
     res, wl, n_act = run_gpu(args)
     K = args.steps
     t = res["mrab"]["time_s"]

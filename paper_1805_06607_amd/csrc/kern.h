@@ -54,19 +54,13 @@ struct StateSrc {
 };
 
 // donor gather of one link (receivers of one grid taking data from one donor
-// grid) for nj target times at once: lanes (slot j, receiver k, entry e).
-// Slot j reads the donor state y, or y + sum_h beta[j][h] hist[h] when
-// mid[j] (the donor grid's extrapolant, frozen between its own steps), and
-// writes the receiver rows out[j].
+// grid) for nj target times at once: lanes (slot j, receiver k, entry e); slot
+// j reads the donor state ys[j] and writes the receiver rows out[j]
 constexpr int MAXJ = 8;
 struct DonorLink {
     GridDev g;                 // donor grid
-    const double *y;
-    int m;
-    const double *hist[MAXH];
     int nj;
-    int mid[MAXJ];
-    double beta[MAXJ][MAXH];
+    const double *ys[MAXJ];
     double *out[MAXJ];
     Phys ph;
     int32_t row0;              // row of the link's first receiver
@@ -77,11 +71,26 @@ struct DonorLink {
     int sbp;
 };
 
+// extrapolated donor states at listed points for nj target times:
+// out[j][v*N + p] = y[v*N + p] + sum_h beta[j][h] hist[h][v*N + p]
+struct Extrap {
+    const double *y;
+    int m, nv;
+    int64_t N;
+    const double *hist[MAXH];
+    int nj;
+    double beta[MAXJ][MAXH];
+    double *out[MAXJ];
+    const int32_t *pts;
+    int64_t np;
+};
+
 // ---------------------------------------------------------------- launches
 hipError_t launch_grad(const GridDev &g, int sbp, double gm1, const double *q, double *grad, hipStream_t st);
 hipError_t launch_rhs(const GridDev &g, const GridDev *g_dev, int sbp, const Phys &ph, const double *q,
                       const double *grad, double *F, const Combine &cb, hipStream_t st);
 hipError_t launch_donor(const DonorLink &a, hipStream_t st);
+hipError_t launch_extrap(const Extrap &a, hipStream_t st);
 // fused LDS-tiled 2D right-hand side (gradients, fluxes, divergence, SAT, AB update)
 hipError_t launch_rhs_tile2d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *F,
                              const Combine &cb, hipStream_t st);

@@ -442,7 +442,8 @@ __global__ void __launch_bounds__(256) k_rhs(GridDev g, Phys ph, const double *_
 }
 
 // ------------------------------------------- fused LDS-tiled 2D right-hand side
-// One workgroup of 256 threads computes a 32 x 8 tile of outputs in one pass:
+// One workgroup of TX*TY threads computes a TX x TY tile of outputs (one per
+// thread) in one pass:
 //   1. primitives (rho, u, v, T) and class bytes on the tile plus a halo of HP
 //      points, metric terms on the flux region, all staged in LDS (every
 //      global load of the phase is issued before the first use);
@@ -454,9 +455,9 @@ __global__ void __launch_bounds__(256) k_rhs(GridDev g, Phys ph, const double *_
 // for SBP 2-1), so outputs need fluxes within HF = R and every flux point of
 // that region has its whole stencil inside HP = HF + R, whatever the run
 // layout.
-template <int SBP>
+template <int SBP, int TX_, int TY_>
 struct TileCfg {
-    static constexpr int TX = 32, TY = 8, NT = 256;
+    static constexpr int TX = TX_, TY = TY_, NT = TX_ * TY_;
     static constexpr int R = SBP == 42 ? 3 : 1;
     static constexpr int HF = R, HP = 2 * R;
     static constexpr int PX = TX + 2 * HP, PY = TY + 2 * HP, PN = PX * PY;
@@ -465,11 +466,22 @@ struct TileCfg {
     static constexpr int NIT = (PN + NT - 1) / NT;
 };
 
-template <int SBP, int CART>
-__global__ void __launch_bounds__(256) k_rhs_tile2d(GridDev g, Phys ph, const double *__restrict__ q,
-                                                    double *__restrict__ F, Combine cb, int ntx, int nty)
+// periodic wrap of a line index (the remainder is taken only off the line)
+__device__ __forceinline__ int wrap1(int i, int n)
 {
-    using C = TileCfg<SBP>;
+    if (i < 0 || i >= n) {
+        i %= n;
+        if (i < 0) i += n;
+    }
+    return i;
+}
+
+template <int SBP, int CART, int TX_, int TY_>
+__global__ void __launch_bounds__(TX_ * TY_) k_rhs_tile2d(GridDev g, Phys ph, const double *__restrict__ q,
+                                                         double *__restrict__ F, Combine cb, int ntx, int nty)
+{
+    using C = TileCfg<SBP, TX_, TY_>;
+    constexpr int NT = C::NT;
     constexpr int TX = C::TX, TY = C::TY, HF = C::HF, HP = C::HP, PX = C::PX, PY = C::PY, PN = C::PN;
     constexpr int MX = C::MX, MN = C::MN;
     __shared__ double sP[4][PY][PX];                 // rho, u, v, T
@@ -489,20 +501,43 @@ __global__ void __launch_bounds__(256) k_rhs_tile2d(GridDev g, Phys ph, const do
     const double gm1 = ph.gamma - 1.0;
     const int tid = threadIdx.x;
 
+    // the thread's output point; its state and older history values are only
+    // needed in the epilogue, so they are requested first
+    const int tx = tid % TX, ty = tid / TX;
+    const int cxo = HP + tx, cyo = HP + ty;
+    const int gxo = x0 + tx, gyo = y0 + ty;
+    const bool inside = gxo < nx && gyo < ny;
+    const int64_t po = inside ? (int64_t)gyo * nx + gxo : 0;
+    // (small, latency-bound tiles only: on large tiles the long live ranges
+    // cost more occupancy than the early loads save)
+    constexpr bool EARLY = TX_ * TY_ <= 128;
+    double hq[4], hv[MAXH - 1][4];
+    auto load_epilogue = [&]() {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) hq[v] = inside ? q[v * N + po] : 0.0;
+#pragma unroll
+        for (int j = 0; j < MAXH - 1; ++j)
+            if (j < cb.m - 1 && inside) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) hv[j][v] = cb.hist[j][v * N + po];
+            }
+    };
+    if constexpr (EARLY) load_epilogue();
+
     // 1. stage: issue every load first
     double lq[C::NIT][4];
     int8_t lc[C::NIT][2];
 #pragma unroll
     for (int it = 0; it < C::NIT; ++it) {
-        int e = tid + it * 256;
+        int e = tid + it * NT;
         lq[it][0] = lq[it][1] = lq[it][2] = lq[it][3] = 0.0;
         lc[it][0] = lc[it][1] = (int8_t)CLS_HOLE;
         if (e < PN) {
             int cx = e % PX, cy = e / PX;
             int gx = x0 - HP + cx, gy = y0 - HP + cy;
             bool ok = true;
-            if (g.periodic[0]) gx = (gx % nx + nx) % nx; else ok = ok && gx >= 0 && gx < nx;
-            if (g.periodic[1]) gy = (gy % ny + ny) % ny; else ok = ok && gy >= 0 && gy < ny;
+            if (g.periodic[0]) gx = wrap1(gx, nx); else ok = ok && gx >= 0 && gx < nx;
+            if (g.periodic[1]) gy = wrap1(gy, ny); else ok = ok && gy >= 0 && gy < ny;
             if (ok) {
                 int64_t p = (int64_t)gy * nx + gx;
                 lc[it][0] = g.cls[p];
@@ -515,20 +550,32 @@ __global__ void __launch_bounds__(256) k_rhs_tile2d(GridDev g, Phys ph, const do
         }
     }
     if constexpr (!CART) {
-        for (int e = tid; e < MN; e += 256) {
+        constexpr int MIT = (MN + NT - 1) / NT;
+        double lm[MIT][5];
+#pragma unroll
+        for (int it = 0; it < MIT; ++it) {
+            int e = tid + it * NT;
             int mx = e % MX, my = e / MX;
             int gx = x0 - HF + mx, gy = y0 - HF + my;
-            bool ok = true;
-            if (g.periodic[0]) gx = (gx % nx + nx) % nx; else ok = ok && gx >= 0 && gx < nx;
-            if (g.periodic[1]) gy = (gy % ny + ny) % ny; else ok = ok && gy >= 0 && gy < ny;
+            bool ok = e < MN;
+            if (g.periodic[0]) gx = wrap1(gx, nx); else ok = ok && gx >= 0 && gx < nx;
+            if (g.periodic[1]) gy = wrap1(gy, ny); else ok = ok && gy >= 0 && gy < ny;
             int64_t p = ok ? (int64_t)gy * nx + gx : 0;
 #pragma unroll
-            for (int k = 0; k < 5; ++k) sM[k][e] = ok ? g.metric[k * N + p] : 0.0;
+            for (int kk = 0; kk < 5; ++kk) lm[it][kk] = ok ? g.metric[kk * N + p] : 0.0;
+        }
+#pragma unroll
+        for (int it = 0; it < MIT; ++it) {
+            int e = tid + it * NT;
+            if (e < MN) {
+#pragma unroll
+                for (int kk = 0; kk < 5; ++kk) sM[kk][e] = lm[it][kk];
+            }
         }
     }
 #pragma unroll
     for (int it = 0; it < C::NIT; ++it) {
-        int e = tid + it * 256;
+        int e = tid + it * NT;
         if (e < PN) {
             int cx = e % PX, cy = e / PX;
             double r0 = 0.0, u = 0.0, v = 0.0, T = 0.0;
@@ -610,11 +657,6 @@ __global__ void __launch_bounds__(256) k_rhs_tile2d(GridDev g, Phys ph, const do
         }
     };
 
-    // the output point of this thread
-    const int tx = tid % TX, ty = tid / TX;
-    const int cxo = HP + tx, cyo = HP + ty;
-    const int gxo = x0 + tx, gyo = y0 + ty;
-    const bool inside = gxo < nx && gyo < ny;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 
 #pragma unroll
@@ -622,7 +664,7 @@ __global__ void __launch_bounds__(256) k_rhs_tile2d(GridDev g, Phys ph, const do
         const int FX = m == 0 ? TX + 2 * HF : TX;
         const int FY = m == 0 ? TY : TY + 2 * HF;
         const int ox = m == 0 ? HF : 0, oy = m == 0 ? 0 : HF;
-        for (int e = tid; e < FX * FY; e += 256) {
+        for (int e = tid; e < FX * FY; e += NT) {
             int fx = e % FX, fy = e / FX;
             int cx = HP - ox + fx, cy = HP - oy + fy;
             double f[4] = {0.0, 0.0, 0.0, 0.0};
@@ -652,7 +694,8 @@ __global__ void __launch_bounds__(256) k_rhs_tile2d(GridDev g, Phys ph, const do
 
     // 3. epilogue
     if (!inside) return;
-    const int64_t p = (int64_t)gyo * nx + gxo;
+    if constexpr (!EARLY) load_epilogue();
+    const int64_t p = po;
     const int cx0 = sC[0][cyo][cxo], cy0 = sC[1][cyo][cxo];
     double r[4];
     if ((cx0 & 15) == CLS_HOLE) {
@@ -663,8 +706,7 @@ __global__ void __launch_bounds__(256) k_rhs_tile2d(GridDev g, Phys ph, const do
 #pragma unroll
         for (int v = 0; v < 4; ++v) r[v] = -J * acc[v];
         if (((cx0 >> 4) & 3) | ((cy0 >> 4) & 3)) {
-            double qp[4];
-            load_q<2>(q, N, p, qp);
+            double qp[4] = {hq[0], hq[1], hq[2], hq[3]};
             double gr[3][2];
             grad_at(cxo, cyo, gr);
             double uu[2] = {sP[1][cyo][cxo], sP[2][cyo][cxo]};
@@ -727,16 +769,9 @@ __global__ void __launch_bounds__(256) k_rhs_tile2d(GridDev g, Phys ph, const do
 #pragma unroll
     for (int v = 0; v < 4; ++v) F[v * N + p] = r[v];
     if (cb.m > 0) {
-        double hv[MAXH - 1][4];
-#pragma unroll
-        for (int j = 0; j < MAXH - 1; ++j)
-            if (j < cb.m - 1) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) hv[j][v] = cb.hist[j][v * N + p];
-            }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            double a2 = q[v * N + p];
+            double a2 = hq[v];
 #pragma unroll
             for (int j = 0; j < MAXH - 1; ++j)
                 if (j < cb.m - 1) a2 = add_nc(a2, cb.c[j], hv[j][v]);
@@ -767,32 +802,18 @@ __global__ void __launch_bounds__(256) k_donor(DonorLink a)
     const int64_t p = a.pts[ent];
     const double w = a.w[ent];
     const int64_t N = a.g.npts;
-    const double *__restrict__ y = a.y;
-    const int m = a.m;
-    // the slot's extrapolation row and output, selected with constant indices
-    int mid = 0;
-    double bj[MAXH];
+    // the slot's state and output, selected with constant indices
+    const double *y = nullptr;
     double *outp = nullptr;
 #pragma unroll
     for (int jj = 0; jj < MAXJ; ++jj)
         if (jj == j) {
-            mid = a.mid[jj];
+            y = a.ys[jj];
             outp = a.out[jj];
-#pragma unroll
-            for (int hh = 0; hh < MAXH; ++hh) bj[hh] = a.beta[jj][hh];
         }
     auto qload = [&](int64_t idx, double *o) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            int64_t el = v * N + idx;
-            double acc = y[el];
-            if (mid) {
-#pragma unroll
-                for (int hh = 0; hh < MAXH; ++hh)
-                    if (hh < m) acc = add_nc(acc, bj[hh], a.hist[hh][el]);
-            }
-            o[v] = acc;
-        }
+        for (int v = 0; v < NV; ++v) o[v] = y[v * N + idx];
     };
     double qp[NV];
     qload(p, qp);
@@ -824,6 +845,46 @@ __global__ void __launch_bounds__(256) k_donor(DonorLink a)
 #pragma unroll
         for (int t = 0; t < RB; ++t) o[t] = val[t];
     }
+}
+
+// extrapolated donor states at the donor-stencil points of mid-step links:
+// one lane per (slot, point, variable)
+__global__ void __launch_bounds__(256) k_extrap(Extrap a)
+{
+    int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = a.np * a.nv;
+    const int j = (int)(lane / per);
+    if (j >= a.nj) return;
+    const int64_t rem = lane - (int64_t)j * per;
+    const int v = (int)(rem / a.np);
+    const int64_t i = rem - (int64_t)v * a.np;
+    const int64_t el = (int64_t)v * a.N + a.pts[i];
+    double bj[MAXH];
+    double *outp = nullptr;
+#pragma unroll
+    for (int jj = 0; jj < MAXJ; ++jj)
+        if (jj == j) {
+            outp = a.out[jj];
+#pragma unroll
+            for (int hh = 0; hh < MAXH; ++hh) bj[hh] = a.beta[jj][hh];
+        }
+    double hv[MAXH];
+#pragma unroll
+    for (int hh = 0; hh < MAXH; ++hh)
+        if (hh < a.m) hv[hh] = a.hist[hh][el];
+    double acc = a.y[el];
+#pragma unroll
+    for (int hh = 0; hh < MAXH; ++hh)
+        if (hh < a.m) acc = add_nc(acc, bj[hh], hv[hh]);
+    outp[el] = acc;
+}
+
+hipError_t launch_extrap(const Extrap &a, hipStream_t st)
+{
+    if (a.np == 0 || a.nj == 0) return hipSuccess;
+    int64_t lanes = a.np * a.nv * a.nj;
+    hipLaunchKernelGGL(k_extrap, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- elementwise
@@ -986,21 +1047,31 @@ hipError_t launch_rhs(const GridDev &g, const GridDev *, int sbp, const Phys &ph
     return hipGetLastError();
 }
 
+template <int TX, int TY>
+static hipError_t tile2d_shape(const GridDev &g, int sbp, const Phys &ph, const double *q, double *F,
+                               const Combine &cb, hipStream_t st)
+{
+    int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY;
+    dim3 grid(ntx * nty), blk(TX * TY);
+    if (sbp == 21 && g.cartesian)
+        hipLaunchKernelGGL((k_rhs_tile2d<21, 1, TX, TY>), grid, blk, 0, st, g, ph, q, F, cb, ntx, nty);
+    else if (sbp == 21)
+        hipLaunchKernelGGL((k_rhs_tile2d<21, 0, TX, TY>), grid, blk, 0, st, g, ph, q, F, cb, ntx, nty);
+    else if (g.cartesian)
+        hipLaunchKernelGGL((k_rhs_tile2d<42, 1, TX, TY>), grid, blk, 0, st, g, ph, q, F, cb, ntx, nty);
+    else
+        hipLaunchKernelGGL((k_rhs_tile2d<42, 0, TX, TY>), grid, blk, 0, st, g, ph, q, F, cb, ntx, nty);
+    return hipGetLastError();
+}
+
+// large grids: 32 x 16 tiles (512 threads, less halo per output); small
+// grids: 16 x 8 tiles (more workgroups to spread over the 256 CUs)
 hipError_t launch_rhs_tile2d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *F,
                              const Combine &cb, hipStream_t st)
 {
     if (g.dim != 2) return hipErrorInvalidValue;
-    int ntx = (g.n[0] + 31) / 32, nty = (g.n[1] + 7) / 8;
-    dim3 grid(ntx * nty);
-    if (sbp == 21 && g.cartesian)
-        hipLaunchKernelGGL((k_rhs_tile2d<21, 1>), grid, dim3(256), 0, st, g, ph, q, F, cb, ntx, nty);
-    else if (sbp == 21)
-        hipLaunchKernelGGL((k_rhs_tile2d<21, 0>), grid, dim3(256), 0, st, g, ph, q, F, cb, ntx, nty);
-    else if (g.cartesian)
-        hipLaunchKernelGGL((k_rhs_tile2d<42, 1>), grid, dim3(256), 0, st, g, ph, q, F, cb, ntx, nty);
-    else
-        hipLaunchKernelGGL((k_rhs_tile2d<42, 0>), grid, dim3(256), 0, st, g, ph, q, F, cb, ntx, nty);
-    return hipGetLastError();
+    if (g.npts >= (int64_t)128 * 1024) return tile2d_shape<32, 16>(g, sbp, ph, q, F, cb, st);
+    return tile2d_shape<16, 8>(g, sbp, ph, q, F, cb, st);
 }
 
 #define DISPATCH_GRAD(DIM, SBP, CART) \

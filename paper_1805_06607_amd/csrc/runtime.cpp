@@ -44,6 +44,11 @@ struct GridHost {
     int32_t *recv_idx_d = nullptr;
     GridDev dev{};
     int head = 0;
+    // donor grid stepping slower than the fastest grid: its extrapolated
+    // states at the points its donor stencils read, one buffer per mid-step
+    std::vector<int32_t> closure;     // sorted donor-stencil points
+    int32_t *closure_d = nullptr;
+    std::vector<double *> ext;        // per mid-step offset jp = 1..per-1
 };
 
 }  // namespace
@@ -242,6 +247,55 @@ bool is_iface(const GridHost &g, int64_t p)
     return false;
 }
 
+// offsets of the first-derivative row selected by a class code (the rows of
+// the SBP operators used by the kernels)
+void row_offsets(int sbp, int row, std::vector<int> &o)
+{
+    o.clear();
+    if (sbp == 21) {
+        if (row == 0) o = {-1, 1};
+        else if (row == 1) o = {0, 1};
+        else o = {0, -1};
+        return;
+    }
+    switch (row) {
+    case 0: o = {-2, -1, 1, 2}; break;
+    case 1: o = {0, 1, 2, 3}; break;
+    case 2: o = {-1, 1}; break;
+    case 3: o = {-2, -1, 1, 2}; break;
+    case 4: o = {-3, -1, 1, 2}; break;
+    case 5: o = {0, -1, -2, -3}; break;
+    case 6: o = {1, -1}; break;
+    case 7: o = {2, 1, -1, -2}; break;
+    default: o = {3, 1, -1, -2}; break;
+    }
+}
+
+// points read by the donor kernel on donor grid D: every donor point and the
+// points of its gradient stencil in each direction
+void build_closure(const mr_ctx *c, int d, GridHost &D)
+{
+    std::vector<char> mark(D.npts, 0);
+    std::vector<int> off;
+    for (size_t e = 0; e < c->ept.size(); ++e) {
+        if (c->egrid[e] != d) continue;
+        int64_t p = c->ept[e];
+        mark[p] = 1;
+        int ic[3] = {(int)(p % D.n[0]), (int)((p / D.n[0]) % D.n[1]), (int)(p / ((int64_t)D.n[0] * D.n[1]))};
+        for (int m = 0; m < D.dim; ++m) {
+            row_offsets(c->P.sbp, D.cls[(size_t)m * D.npts + p] & 15, off);
+            for (int o : off) {
+                int j = ic[m] + o;
+                if (D.periodic[m]) j = ((j % D.n[m]) + D.n[m]) % D.n[m];
+                mark[p + (int64_t)(j - ic[m]) * D.stride[m]] = 1;
+            }
+        }
+    }
+    D.closure.clear();
+    for (int64_t p = 0; p < D.npts; ++p)
+        if (mark[p]) D.closure.push_back((int32_t)p);
+}
+
 struct Carver {
     char *base;
     size_t off = 0;
@@ -275,6 +329,10 @@ size_t layout(mr_ctx *c, char *base)
         size_t nr = g.recv_pts.size();
         g.recv_idx_d = nr ? cv.take<int32_t>((size_t)N) : nullptr;
         g.recv_buf = nr ? cv.take<double>(nr * (nv + g.dim * (nv - 1)) * c->rmax) : nullptr;
+        int per = c->rmax / g.rate;
+        g.ext.assign(per > 1 && !g.closure.empty() ? per - 1 : 0, nullptr);
+        for (auto &e : g.ext) e = cv.take<double>((size_t)nv * N);
+        g.closure_d = g.closure.empty() ? nullptr : cv.take<int32_t>(g.closure.size());
     }
     size_t R = c->rgrid.size();
     c->ept_d = cv.take<int32_t>(R * c->S + 1);
@@ -317,37 +375,62 @@ mrk::DonorLink link_base(const mr_ctx *c, const Link &L)
 int link_current(mr_ctx *c, const Link &L, const double *y, double *out)
 {
     mrk::DonorLink a = link_base(c, L);
-    a.y = y;
     a.nj = 1;
-    a.mid[0] = 0;
+    a.ys[0] = y;
     a.out[0] = out;
     HIPCHK(c, mrk::launch_donor(a, c->st));
     return MR_OK;
 }
 
-// right after donor grid d evaluated at micro-time k: donor data for every
-// later micro-time k' < k + per_d at which the receiving grid evaluates and d
-// is mid-step, from d's extrapolant (frozen until d's next step)
-int link_future(mr_ctx *c, const Link &L, int k)
+// right after donor grid d evaluated at micro-time k: its extrapolant is
+// fixed until its next step, so the donor data of every later micro-time
+// k' < k + per_d at which a receiving grid evaluates is gathered now:
+// first the extrapolated states at the donor-stencil points (one buffer per
+// offset), then one batched gather per link
+int donor_future(mr_ctx *c, int d, int k)
 {
-    const GridHost &D = c->G[L.dg];
-    const GridHost &R = c->G[L.rg];
-    int per_d = c->rmax / D.rate, per_g = c->rmax / R.rate;
-    mrk::DonorLink a = link_base(c, L);
-    a.y = D.y[D.cur];
-    a.m = c->P.hist_len;
-    for (int j = 0; j < a.m; ++j) a.hist[j] = slot(c, D, j);
-    a.nj = 0;
-    for (int jp = 1; jp < per_d; ++jp) {
-        int kp = k + jp;
-        if (kp > c->rmax) kp -= c->rmax;
-        if (kp % per_g) continue;
-        a.mid[a.nj] = 1;
-        for (int j = 0; j < a.m; ++j) a.beta[a.nj][j] = c->beta[L.dg][jp][j];
-        a.out[a.nj] = recv_slice(c, R, kp);
-        a.nj++;
+    GridHost &D = c->G[d];
+    int per_d = c->rmax / D.rate;
+    if (per_d == 1 || D.closure.empty()) return MR_OK;
+    auto kprime = [&](int jp) { int kp = k + jp; return kp > c->rmax ? kp - c->rmax : kp; };
+    mrk::Extrap x{};
+    x.y = D.y[D.cur];
+    x.m = c->P.hist_len;
+    x.nv = D.dim + 2;
+    x.N = D.npts;
+    for (int j = 0; j < x.m; ++j) x.hist[j] = slot(c, D, j);
+    x.pts = D.closure_d;
+    x.np = (int64_t)D.closure.size();
+    bool need[mrk::MAXJ + 1] = {};
+    for (const Link &L : c->links) {
+        if (L.dg != d) continue;
+        int per_g = c->rmax / c->G[L.rg].rate;
+        for (int jp = 1; jp < per_d; ++jp)
+            if (kprime(jp) % per_g == 0) need[jp] = true;
     }
-    if (a.nj) HIPCHK(c, mrk::launch_donor(a, c->st));
+    x.nj = 0;
+    for (int jp = 1; jp < per_d; ++jp) {
+        if (!need[jp]) continue;
+        for (int j = 0; j < x.m; ++j) x.beta[x.nj][j] = c->beta[d][jp][j];
+        x.out[x.nj] = D.ext[jp - 1];
+        x.nj++;
+    }
+    HIPCHK(c, mrk::launch_extrap(x, c->st));
+    for (const Link &L : c->links) {
+        if (L.dg != d) continue;
+        const GridHost &R = c->G[L.rg];
+        int per_g = c->rmax / R.rate;
+        mrk::DonorLink a = link_base(c, L);
+        a.nj = 0;
+        for (int jp = 1; jp < per_d; ++jp) {
+            int kp = kprime(jp);
+            if (kp % per_g) continue;
+            a.ys[a.nj] = D.ext[jp - 1];
+            a.out[a.nj] = recv_slice(c, R, kp);
+            a.nj++;
+        }
+        if (a.nj) HIPCHK(c, mrk::launch_donor(a, c->st));
+    }
     return MR_OK;
 }
 
@@ -530,6 +613,8 @@ int mr_finalize(mr_ctx *c, size_t *bytes)
             if (!ab_alpha(n, m, (long double)jp / (long double)per, c->alpha_mid[g][jp]))
                 return fail(c, MR_ERR_SETUP, "AB coefficients");
     }
+    for (size_t g = 0; g < c->G.size(); ++g)
+        if (c->G[g].rate < c->rmax) build_closure(c, (int)g, c->G[g]);
     c->ws_bytes = layout(c, nullptr);
     c->finalized = true;
     *bytes = c->ws_bytes;
@@ -552,6 +637,9 @@ int mr_bind_workspace(mr_ctx *c, void *dev, size_t bytes)
         HIPCHK(c, hipMemcpyAsync(g.cls_d, g.cls.data(), g.cls.size(), hipMemcpyHostToDevice, c->st));
         if (!g.recv_pts.empty())
             HIPCHK(c, hipMemcpyAsync(g.recv_idx_d, g.recv_idx.data(), g.recv_idx.size() * 4, hipMemcpyHostToDevice,
+                                     c->st));
+        if (!g.closure.empty())
+            HIPCHK(c, hipMemcpyAsync(g.closure_d, g.closure.data(), g.closure.size() * 4, hipMemcpyHostToDevice,
                                      c->st));
         GridDev &D = g.dev;
         D.dim = g.dim;
@@ -744,8 +832,8 @@ int mr_mrab_start(mr_ctx *c, double t0)
     }
     // every grid has just evaluated: donor data of the first macrostep's
     // mid-step times
-    for (const Link &L : c->links) {
-        int rc = link_future(c, L, c->rmax);
+    for (int g = 0; g < (int)c->G.size(); ++g) {
+        int rc = donor_future(c, g, c->rmax);
         if (rc) return rc;
     }
     c->t = t0 + nsteps * d;
@@ -788,9 +876,9 @@ int mr_mrab_macrostep(mr_ctx *c, int nsteps)
                 if (rc) return rc;
                 Gh.head = (Gh.head + 1) % m;
             }
-            for (const Link &L : c->links) {
-                if (!ends[L.dg] || c->G[L.dg].rate == c->rmax) continue;
-                int rc = link_future(c, L, k);
+            for (int g = 0; g < G; ++g) {
+                if (!ends[g]) continue;
+                int rc = donor_future(c, g, k);
                 if (rc) return rc;
             }
         }
