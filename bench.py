@@ -46,6 +46,46 @@ def workload(rates=(1, 4)):
     return wl
 
 
+def run_tgv3d(args):
+    """Secondary mode: the 3D three-level case (192^3 background, two 96^3
+    patches, one 64^3 patch; rates 1, 2, 2, 4; SBP 4-2, AB3) -- the
+    HBM-bound configuration.  Prints one JSON line of its own."""
+    import torch
+    import workloads
+    from paper_1805_06607_amd.system import System
+    wl = workloads.tgv3d()
+    log("setup 3D system")
+    s = System(wl)
+    h, H = s.timestep()
+    s.start(0.0)
+    n_act = active_counts(s)
+    pts = sum(g.rate * n for g, n in zip(wl.grids, n_act))
+    s.macrostep(args.warmup)
+    s.kernel_timing(0, args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.macrostep(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ktot, kc = s.kernel_time()
+    s.guard()
+    bpp = bytes_per_point(wl, 0)
+    per_launch = n_act[0] * bpp
+    avg = ktot / max(kc, 1) * 1e-3
+    ach = per_launch / avg / 1e9
+    line = {"metric": "MRAB pt-updates/s (3D three-level case), 1 GPU", "value": pts * args.steps / el,
+            "unit": "pt-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "3D periodic 192^3 + 2 x 96^3 (half spacing) + 64^3 (quarter spacing), "
+                                   "SBP 4-2, cubic donors, AB3, rates 1/2/2/4, Re 1600, M 0.3",
+                       "points_active": n_act, "H": H},
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "background-grid right-hand-side step", "bytes_per_launch": per_launch,
+                         "bytes_per_point": bpp, "avg_launch_us": avg * 1e6, "launches_timed": kc}}
+    print(json.dumps(line), flush=True)
+
+
 def active_counts(sysg):
     return [int(ib.sum()) for ib in sysg.iblanks]
 
@@ -223,6 +263,7 @@ def main():
     ap.add_argument("--ee-macrosteps", type=int, default=200)
     ap.add_argument("--ee-spinup", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--workload", default="cylinder", choices=["cylinder", "tgv3d"])
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -239,6 +280,9 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {args.calibrate_copy_mib} MiB read + {args.calibrate_copy_mib} MiB written")
         del a, c
+    if args.workload == "tgv3d":
+        run_tgv3d(args)
+        return
     res, wl, n_act = run_gpu(args)
     K = args.steps
     t = res["mrab"]["time_s"]

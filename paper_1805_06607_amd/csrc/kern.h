@@ -53,18 +53,24 @@ struct StateSrc {
     const double *hist[MAXH];
 };
 
-// donor gather of one link (receivers of one grid taking data from one donor
-// grid) for nj target times at once: lanes (slot j, receiver k, entry e); slot
-// j reads the donor state ys[j] and writes the receiver rows out[j]
+// donor data of one link (receivers of one grid taking data from one donor
+// grid) for nj target times at once, in two launches:
+//   values: one lane per (slot j, unique donor point u): q and the Cartesian
+//           viscous fluxes at the point from state ys[j] -> vals[j][u][RB]
+//   gather: one lane per (slot j, receiver k): sum_e w[k][e] vals[j][uid[k][e]]
+//           in entry order -> out[j] row (row0 + k)
 constexpr int MAXJ = 8;
 struct DonorLink {
     GridDev g;                 // donor grid
     int nj;
     const double *ys[MAXJ];
     double *out[MAXJ];
+    double *vals;              // nj x nu x RB scratch
     Phys ph;
     int32_t row0;              // row of the link's first receiver
-    const int32_t *pts;        // nrecv x S donor points
+    const int32_t *upts;       // nu unique donor points
+    int64_t nu;
+    const int32_t *uid;        // nrecv x S indices into upts
     const double *w;           // nrecv x S weights
     int64_t nrecv;
     int S;

@@ -477,7 +477,7 @@ __device__ __forceinline__ int wrap1(int i, int n)
 }
 
 template <int SBP, int CART, int TX_, int TY_>
-__global__ void __launch_bounds__(TX_ * TY_) k_rhs_tile2d(GridDev g, Phys ph, const double *__restrict__ q,
+__global__ void __launch_bounds__(TX_ * TY_, 2) k_rhs_tile2d(GridDev g, Phys ph, const double *__restrict__ q,
                                                          double *__restrict__ F, Combine cb, int ntx, int nty)
 {
     using C = TileCfg<SBP, TX_, TY_>;
@@ -511,18 +511,18 @@ __global__ void __launch_bounds__(TX_ * TY_) k_rhs_tile2d(GridDev g, Phys ph, co
     // (small, latency-bound tiles only: on large tiles the long live ranges
     // cost more occupancy than the early loads save)
     constexpr bool EARLY = TX_ * TY_ <= 128;
-    double hq[4], hv[MAXH - 1][4];
-    auto load_epilogue = [&]() {
+    constexpr int HV = EARLY ? MAXH - 1 : 1;
+    double hq[4], hv[HV][4];
+    if constexpr (EARLY) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) hq[v] = inside ? q[v * N + po] : 0.0;
 #pragma unroll
-        for (int j = 0; j < MAXH - 1; ++j)
+        for (int j = 0; j < HV; ++j)
             if (j < cb.m - 1 && inside) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) hv[j][v] = cb.hist[j][v * N + po];
             }
-    };
-    if constexpr (EARLY) load_epilogue();
+    }
 
     // 1. stage: issue every load first
     double lq[C::NIT][4];
@@ -694,7 +694,10 @@ __global__ void __launch_bounds__(TX_ * TY_) k_rhs_tile2d(GridDev g, Phys ph, co
 
     // 3. epilogue
     if (!inside) return;
-    if constexpr (!EARLY) load_epilogue();
+    if constexpr (!EARLY) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) hq[v] = q[v * N + po];
+    }
     const int64_t p = po;
     const int cx0 = sC[0][cyo][cxo], cy0 = sC[1][cyo][cxo];
     double r[4];
@@ -774,7 +777,12 @@ __global__ void __launch_bounds__(TX_ * TY_) k_rhs_tile2d(GridDev g, Phys ph, co
             double a2 = hq[v];
 #pragma unroll
             for (int j = 0; j < MAXH - 1; ++j)
-                if (j < cb.m - 1) a2 = add_nc(a2, cb.c[j], hv[j][v]);
+                if (j < cb.m - 1) {
+                    double h;
+                    if constexpr (EARLY) h = hv[j < HV ? j : 0][v];
+                    else h = cb.hist[j][v * N + p];
+                    a2 = add_nc(a2, cb.c[j], h);
+                }
             a2 = add_nc(a2, cb.c[cb.m - 1], r[v]);
             cb.y_next[v * N + p] = a2;
         }
@@ -782,35 +790,23 @@ __global__ void __launch_bounds__(TX_ * TY_) k_rhs_tile2d(GridDev g, Phys ph, co
 }
 
 // ---------------------------------------------------------------- donors
-// One lane per (receiver, stencil entry): donor state (extrapolated in time
-// when the donor grid is mid-step), donor viscous flux from the donor grid's
-// own SBP gradient, times the weight; a fixed butterfly over the S lanes of a
-// receiver sums the stencil.
+// Donor values: q and the Cartesian viscous flux vectors at each unique donor
+// point, from the donor grid's state and its own SBP gradient.
 template <int DIM, int SBP, int CART>
-__global__ void __launch_bounds__(256) k_donor(DonorLink a)
+__global__ void __launch_bounds__(256) k_donor_vals(DonorLink a)
 {
     constexpr int NV = DIM + 2;
     constexpr int RB = NV + DIM * (NV - 1);
     int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t per_slot = a.nrecv * a.S;
-    const int j = (int)(lane / per_slot);
-    if (j >= a.nj) return;                    // whole groups of S lanes leave together
-    const int64_t rem = lane - (int64_t)j * per_slot;
-    const int64_t k = rem / a.S;
-    const int e = (int)(rem % a.S);
-    const int64_t ent = k * a.S + e;
-    const int64_t p = a.pts[ent];
-    const double w = a.w[ent];
+    const int j = (int)(lane / a.nu);
+    if (j >= a.nj) return;
+    const int64_t u = lane - (int64_t)j * a.nu;
+    const int64_t p = a.upts[u];
     const int64_t N = a.g.npts;
-    // the slot's state and output, selected with constant indices
     const double *y = nullptr;
-    double *outp = nullptr;
 #pragma unroll
     for (int jj = 0; jj < MAXJ; ++jj)
-        if (jj == j) {
-            y = a.ys[jj];
-            outp = a.out[jj];
-        }
+        if (jj == j) y = a.ys[jj];
     auto qload = [&](int64_t idx, double *o) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) o[v] = y[v * N + idx];
@@ -821,21 +817,43 @@ __global__ void __launch_bounds__(256) k_donor(DonorLink a)
     coords(a.g, p, ic);
     double gr[DIM + 1][DIM];
     gradient<DIM, SBP, CART>(a.g, p, ic, a.ph.gamma - 1.0, qload, gr);
+    double u_[DIM];
+    double ri = 1.0 / qp[0];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) u_[i] = qp[1 + i] * ri;
+    double Fv[DIM][DIM + 1];
+    viscous_flux<DIM>(a.ph, u_, gr, Fv);
+    double *o = a.vals + ((int64_t)j * a.nu + u) * RB;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) o[v] = qp[v];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+#pragma unroll
+        for (int v = 1; v < NV; ++v) o[NV + d * (NV - 1) + (v - 1)] = Fv[d][v - 1];
+}
+
+// Receiver rows: Lagrange-weighted sum of the donor values; one lane per
+// (slot, receiver, entry), a fixed butterfly over the S lanes of a receiver.
+template <int RB>
+__global__ void __launch_bounds__(256) k_donor_gather(DonorLink a)
+{
+    int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per_slot = a.nrecv * a.S;
+    const int j = (int)(lane / per_slot);
+    if (j >= a.nj) return;                    // whole groups of S lanes leave together
+    const int64_t rem = lane - (int64_t)j * per_slot;
+    const int64_t k = rem / a.S;
+    const int e = (int)(rem % a.S);
+    double *outp = nullptr;
+#pragma unroll
+    for (int jj = 0; jj < MAXJ; ++jj)
+        if (jj == j) outp = a.out[jj];
+    const int64_t ent = k * a.S + e;
+    const double w = a.w[ent];
+    const double *vrow = a.vals + ((int64_t)j * a.nu + a.uid[ent]) * RB;
     double val[RB];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) val[v] = w * qp[v];
-    {
-        double u[DIM];
-        double ri = 1.0 / qp[0];
-#pragma unroll
-        for (int i = 0; i < DIM; ++i) u[i] = qp[1 + i] * ri;
-        double Fv[DIM][DIM + 1];
-        viscous_flux<DIM>(a.ph, u, gr, Fv);
-#pragma unroll
-        for (int d = 0; d < DIM; ++d)
-#pragma unroll
-            for (int v = 1; v < NV; ++v) val[NV + d * (NV - 1) + (v - 1)] = w * Fv[d][v - 1];
-    }
+    for (int t = 0; t < RB; ++t) val[t] = w * vrow[t];
     for (int off = 1; off < a.S; off <<= 1) {
 #pragma unroll
         for (int t = 0; t < RB; ++t) val[t] += __shfl_xor(val[t], off, 64);
@@ -1090,12 +1108,12 @@ hipError_t launch_grad(const GridDev &g, int sbp, double gm1, const double *q, d
 }
 
 #define DISPATCH_DONOR(DIM, SBP, CART) \
-    hipLaunchKernelGGL((k_donor<DIM, SBP, CART>), dim3(nblk(lanes, 256)), dim3(256), 0, st, a)
+    hipLaunchKernelGGL((k_donor_vals<DIM, SBP, CART>), dim3(nblk(lanes, 256)), dim3(256), 0, st, a)
 
 hipError_t launch_donor(const DonorLink &a, hipStream_t st)
 {
     if (a.nrecv == 0 || a.nj == 0) return hipSuccess;
-    int64_t lanes = a.nrecv * a.S * a.nj;
+    int64_t lanes = a.nu * a.nj;
     const GridDev &g = a.g;
     if (g.dim == 2 && a.sbp == 21 && g.cartesian) DISPATCH_DONOR(2, 21, 1);
     else if (g.dim == 2 && a.sbp == 21) DISPATCH_DONOR(2, 21, 0);
@@ -1104,6 +1122,13 @@ hipError_t launch_donor(const DonorLink &a, hipStream_t st)
     else if (g.dim == 3 && a.sbp == 21 && g.cartesian) DISPATCH_DONOR(3, 21, 1);
     else if (g.dim == 3 && a.sbp == 42 && g.cartesian) DISPATCH_DONOR(3, 42, 1);
     else return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int64_t gl = a.nrecv * a.S * a.nj;
+    if (g.dim == 2)
+        hipLaunchKernelGGL((k_donor_gather<10>), dim3(nblk(gl, 256)), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_donor_gather<17>), dim3(nblk(gl, 256)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

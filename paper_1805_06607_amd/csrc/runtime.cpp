@@ -57,6 +57,9 @@ struct Link {
     int rg, dg;
     int64_t first, n;     // global receiver range
     int32_t row0;         // row of the first receiver in the receiving grid's buffer
+    std::vector<int32_t> upts;   // unique donor points of the link
+    int32_t *upts_d = nullptr;
+    double *vals_d = nullptr;    // r_max x nu x RB donor values
 };
 
 struct mr_ctx {
@@ -80,7 +83,8 @@ struct mr_ctx {
     std::vector<std::vector<double>> c_own;
     std::vector<std::vector<std::vector<double>>> beta;
     std::vector<Link> links;
-    int32_t *ept_d = nullptr;
+    std::vector<int32_t> euid;   // per entry: index into its link's unique points
+    int32_t *euid_d = nullptr;
     double *ew_d = nullptr;
     GridDev *grids_d = nullptr;
     double *partial = nullptr;
@@ -335,8 +339,13 @@ size_t layout(mr_ctx *c, char *base)
         g.closure_d = g.closure.empty() ? nullptr : cv.take<int32_t>(g.closure.size());
     }
     size_t R = c->rgrid.size();
-    c->ept_d = cv.take<int32_t>(R * c->S + 1);
+    c->euid_d = cv.take<int32_t>(R * c->S + 1);
     c->ew_d = cv.take<double>(R * c->S + 1);
+    int RB = (c->P.dim + 2) + c->P.dim * (c->P.dim + 1);
+    for (Link &L : c->links) {
+        L.upts_d = cv.take<int32_t>(L.upts.size() + 1);
+        L.vals_d = cv.take<double>((size_t)c->rmax * L.upts.size() * RB + 1);
+    }
     c->grids_d = cv.take<GridDev>(c->G.size());
     c->partial = cv.take<double>(1024);
     return cv.off + ALIGN;
@@ -363,7 +372,10 @@ mrk::DonorLink link_base(const mr_ctx *c, const Link &L)
     a.g = c->G[L.dg].dev;
     a.ph = c->ph;
     a.row0 = L.row0;
-    a.pts = c->ept_d + L.first * c->S;
+    a.upts = L.upts_d;
+    a.nu = (int64_t)L.upts.size();
+    a.vals = L.vals_d;
+    a.uid = c->euid_d + L.first * c->S;
     a.w = c->ew_d + L.first * c->S;
     a.nrecv = L.n;
     a.S = c->S;
@@ -615,6 +627,15 @@ int mr_finalize(mr_ctx *c, size_t *bytes)
     }
     for (size_t g = 0; g < c->G.size(); ++g)
         if (c->G[g].rate < c->rmax) build_closure(c, (int)g, c->G[g]);
+    c->euid.assign(c->ept.size(), 0);
+    for (Link &L : c->links) {
+        size_t e0 = (size_t)L.first * c->S, e1 = (size_t)(L.first + L.n) * c->S;
+        L.upts.assign(c->ept.begin() + e0, c->ept.begin() + e1);
+        std::sort(L.upts.begin(), L.upts.end());
+        L.upts.erase(std::unique(L.upts.begin(), L.upts.end()), L.upts.end());
+        for (size_t e = e0; e < e1; ++e)
+            c->euid[e] = (int32_t)(std::lower_bound(L.upts.begin(), L.upts.end(), c->ept[e]) - L.upts.begin());
+    }
     c->ws_bytes = layout(c, nullptr);
     c->finalized = true;
     *bytes = c->ws_bytes;
@@ -665,9 +686,11 @@ int mr_bind_workspace(mr_ctx *c, void *dev, size_t bytes)
     }
     size_t R = c->rgrid.size();
     if (R) {
-        HIPCHK(c, hipMemcpyAsync(c->ept_d, c->ept.data(), R * c->S * 4, hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, hipMemcpyAsync(c->euid_d, c->euid.data(), R * c->S * 4, hipMemcpyHostToDevice, c->st));
         HIPCHK(c, hipMemcpyAsync(c->ew_d, c->ew.data(), R * c->S * 8, hipMemcpyHostToDevice, c->st));
     }
+    for (Link &L : c->links)
+        HIPCHK(c, hipMemcpyAsync(L.upts_d, L.upts.data(), L.upts.size() * 4, hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipMemcpyAsync(c->grids_d, devs.data(), devs.size() * sizeof(GridDev), hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
     c->bound = true;
