@@ -181,6 +181,32 @@ int mr_ab_coeffs(int order, int hist_len, double tau, double *out);
 int mr_kernel_timing(mr_ctx *ctx, int grid, int max_events);
 int mr_kernel_time(mr_ctx *ctx, double *total_ms, int *count);
 
+/* Execution options (any time after mr_create; they change the launch plan,
+ * not the method):
+ *  "rhs_two_pass"        1: 2D grids use the gradient pass and the point-wise
+ *                        right-hand-side kernel instead of the fused tile
+ *                        kernel (default 0).
+ * Errors: MR_ERR_ARG (unknown name or bad value). */
+int mr_set_option(mr_ctx *ctx, const char *name, int64_t value);
+
+/* Tile shape of a 2D grid's fused right-hand-side kernel: shape in
+ * 0..MR_NUM_TILE_SHAPES-1, or -1 for the size-based default.  Every shape
+ * evaluates the same formulas per output; results agree up to rounding (the
+ * compiler may fuse a multiply-add differently per shape), and one shape is
+ * bitwise reproducible run to run.  mr_get_tile_shape
+ * reports the shape in use (-1 for 3D grids) and its tile (tx x ty outputs,
+ * tm threads per output).  Errors: MR_ERR_ARG (bad grid or shape),
+ * MR_ERR_UNSUPPORTED (3D grid). */
+enum { MR_NUM_TILE_SHAPES = 8 };
+int mr_set_tile_shape(mr_ctx *ctx, int grid, int shape);
+int mr_get_tile_shape(const mr_ctx *ctx, int grid, int *shape, int *tx, int *ty, int *tm);
+
+/* Autotuner (setup; synchronises): for every 2D grid, time reps launches of
+ * each tile shape on the current state, writing only scratch buffers, and
+ * keep the fastest.  Needs a bound workspace; leaves states, histories and
+ * the schedule untouched. */
+int mr_autotune(mr_ctx *ctx, int reps);
+
 /* Non-finite guard: synchronises, returns MR_ERR_NONFINITE if any state holds
  * a NaN or Inf, and the largest |q| in *maxabs. */
 int mr_guard(mr_ctx *ctx, double *maxabs);

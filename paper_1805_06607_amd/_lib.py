@@ -59,6 +59,10 @@ SIGNATURES = {
     "mr_ab_coeffs": [c_int, c_int, c_double, POINTER(c_double)],
     "mr_kernel_timing": [c_void_p, c_int, c_int],
     "mr_kernel_time": [c_void_p, POINTER(c_double), POINTER(c_int)],
+    "mr_set_option": [c_void_p, c_char_p, c_int64],
+    "mr_set_tile_shape": [c_void_p, c_int, c_int],
+    "mr_get_tile_shape": [c_void_p, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_int)],
+    "mr_autotune": [c_void_p, c_int],
     "mr_guard": [c_void_p, POINTER(c_double)],
     "mr_last_error": [c_void_p],
     "mr_destroy": [c_void_p],

@@ -44,21 +44,12 @@ struct Combine {
     double *y_next;
 };
 
-// state source of a donor grid: y, or y + sum_j beta[j] F_j when the grid is mid-step
-struct StateSrc {
-    const double *y;
-    int mid;
-    int m;
-    double beta[MAXH];
-    const double *hist[MAXH];
-};
-
 // donor data of one link (receivers of one grid taking data from one donor
 // grid) for nj target times at once, in two launches:
 //   values: one lane per (slot j, unique donor point u): q and the Cartesian
 //           viscous fluxes at the point from state ys[j] -> vals[j][u][RB]
-//   gather: one lane per (slot j, receiver k): sum_e w[k][e] vals[j][uid[k][e]]
-//           in entry order -> out[j] row (row0 + k)
+//   gather: one lane per (slot j, receiver k, entry e): w[k][e] vals[j][uid]
+//           summed by a fixed butterfly over e -> out[j] row (row0 + k)
 constexpr int MAXJ = 8;
 struct DonorLink {
     GridDev g;                 // donor grid
@@ -98,8 +89,12 @@ hipError_t launch_rhs(const GridDev &g, const GridDev *g_dev, int sbp, const Phy
 hipError_t launch_donor(const DonorLink &a, hipStream_t st);
 hipError_t launch_extrap(const Extrap &a, hipStream_t st);
 // fused LDS-tiled 2D right-hand side (gradients, fluxes, divergence, SAT, AB update)
+struct TileShape { int tx, ty, tm; };
+constexpr int NUM_TILE_SHAPES = 8;
+extern const TileShape kTileShapes[NUM_TILE_SHAPES];
+int default_tile_shape(const GridDev &g);
 hipError_t launch_rhs_tile2d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *F,
-                             const Combine &cb, hipStream_t st);
+                             const Combine &cb, int shape, hipStream_t st);
 hipError_t launch_combine(int64_t n, const double *y, const Combine &cb, hipStream_t st);
 hipError_t launch_axpy(int64_t n, const double *y, double a, const double *x, double *out, hipStream_t st);
 hipError_t launch_rk3_final(int64_t n, const double *y, double a, const double *k1, const double *k3,

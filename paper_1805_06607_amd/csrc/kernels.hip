@@ -442,8 +442,9 @@ __global__ void __launch_bounds__(256) k_rhs(GridDev g, Phys ph, const double *_
 }
 
 // ------------------------------------------- fused LDS-tiled 2D right-hand side
-// One workgroup of TX*TY threads computes a TX x TY tile of outputs (one per
-// thread) in one pass:
+// One workgroup of TM*TX*TY threads computes a TX x TY tile of outputs in one
+// pass (the first TX*TY threads own one output each; all threads share the
+// staging and flux phases, so small grids can still fill the CUs):
 //   1. primitives (rho, u, v, T) and class bytes on the tile plus a halo of HP
 //      points, metric terms on the flux region, all staged in LDS (every
 //      global load of the phase is issued before the first use);
@@ -455,9 +456,9 @@ __global__ void __launch_bounds__(256) k_rhs(GridDev g, Phys ph, const double *_
 // for SBP 2-1), so outputs need fluxes within HF = R and every flux point of
 // that region has its whole stencil inside HP = HF + R, whatever the run
 // layout.
-template <int SBP, int TX_, int TY_>
+template <int SBP, int TX_, int TY_, int TM_>
 struct TileCfg {
-    static constexpr int TX = TX_, TY = TY_, NT = TX_ * TY_;
+    static constexpr int TX = TX_, TY = TY_, NO = TX_ * TY_, NT = TX_ * TY_ * TM_;
     static constexpr int R = SBP == 42 ? 3 : 1;
     static constexpr int HF = R, HP = 2 * R;
     static constexpr int PX = TX + 2 * HP, PY = TY + 2 * HP, PN = PX * PY;
@@ -476,11 +477,11 @@ __device__ __forceinline__ int wrap1(int i, int n)
     return i;
 }
 
-template <int SBP, int CART, int TX_, int TY_>
-__global__ void __launch_bounds__(TX_ * TY_, 2) k_rhs_tile2d(GridDev g, Phys ph, const double *__restrict__ q,
-                                                         double *__restrict__ F, Combine cb, int ntx, int nty)
+template <int SBP, int CART, int TX_, int TY_, int TM_>
+__global__ void __launch_bounds__(TX_ * TY_ * TM_, 2)
+k_rhs_tile2d(GridDev g, Phys ph, const double *__restrict__ q, double *__restrict__ F, Combine cb, int ntx, int nty)
 {
-    using C = TileCfg<SBP, TX_, TY_>;
+    using C = TileCfg<SBP, TX_, TY_, TM_>;
     constexpr int NT = C::NT;
     constexpr int TX = C::TX, TY = C::TY, HF = C::HF, HP = C::HP, PX = C::PX, PY = C::PY, PN = C::PN;
     constexpr int MX = C::MX, MN = C::MN;
@@ -506,7 +507,7 @@ __global__ void __launch_bounds__(TX_ * TY_, 2) k_rhs_tile2d(GridDev g, Phys ph,
     const int tx = tid % TX, ty = tid / TX;
     const int cxo = HP + tx, cyo = HP + ty;
     const int gxo = x0 + tx, gyo = y0 + ty;
-    const bool inside = gxo < nx && gyo < ny;
+    const bool inside = tid < C::NO && gxo < nx && gyo < ny;
     const int64_t po = inside ? (int64_t)gyo * nx + gxo : 0;
     // (small, latency-bound tiles only: on large tiles the long live ranges
     // cost more occupancy than the early loads save)
@@ -1065,31 +1066,52 @@ hipError_t launch_rhs(const GridDev &g, const GridDev *, int sbp, const Phys &ph
     return hipGetLastError();
 }
 
-template <int TX, int TY>
+template <int TX, int TY, int TM>
 static hipError_t tile2d_shape(const GridDev &g, int sbp, const Phys &ph, const double *q, double *F,
                                const Combine &cb, hipStream_t st)
 {
     int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY;
-    dim3 grid(ntx * nty), blk(TX * TY);
+    dim3 grid(ntx * nty), blk(TX * TY * TM);
     if (sbp == 21 && g.cartesian)
-        hipLaunchKernelGGL((k_rhs_tile2d<21, 1, TX, TY>), grid, blk, 0, st, g, ph, q, F, cb, ntx, nty);
+        hipLaunchKernelGGL((k_rhs_tile2d<21, 1, TX, TY, TM>), grid, blk, 0, st, g, ph, q, F, cb, ntx, nty);
     else if (sbp == 21)
-        hipLaunchKernelGGL((k_rhs_tile2d<21, 0, TX, TY>), grid, blk, 0, st, g, ph, q, F, cb, ntx, nty);
+        hipLaunchKernelGGL((k_rhs_tile2d<21, 0, TX, TY, TM>), grid, blk, 0, st, g, ph, q, F, cb, ntx, nty);
     else if (g.cartesian)
-        hipLaunchKernelGGL((k_rhs_tile2d<42, 1, TX, TY>), grid, blk, 0, st, g, ph, q, F, cb, ntx, nty);
+        hipLaunchKernelGGL((k_rhs_tile2d<42, 1, TX, TY, TM>), grid, blk, 0, st, g, ph, q, F, cb, ntx, nty);
     else
-        hipLaunchKernelGGL((k_rhs_tile2d<42, 0, TX, TY>), grid, blk, 0, st, g, ph, q, F, cb, ntx, nty);
+        hipLaunchKernelGGL((k_rhs_tile2d<42, 0, TX, TY, TM>), grid, blk, 0, st, g, ph, q, F, cb, ntx, nty);
     return hipGetLastError();
 }
 
-// large grids: 32 x 16 tiles (512 threads, less halo per output); small
-// grids: 16 x 8 tiles (more workgroups to spread over the 256 CUs)
+// Tile shapes (TX x TY outputs, TM threads per output).  Every shape evaluates
+// the same formulas per output; results differ at most by rounding, where the
+// compiler contracts a multiply-add differently in one instantiation.
+const TileShape kTileShapes[NUM_TILE_SHAPES] = {
+    {32, 16, 1}, {16, 8, 1}, {16, 8, 2}, {16, 8, 4}, {32, 8, 1}, {32, 8, 2}, {16, 16, 1}, {16, 16, 2},
+};
+
+// default: large grids 32 x 16 (less halo per output); small grids 16 x 8
+// with four threads per output (enough waves to cover the 256 CUs)
+int default_tile_shape(const GridDev &g)
+{
+    return g.npts >= (int64_t)128 * 1024 ? 0 : 3;
+}
+
 hipError_t launch_rhs_tile2d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *F,
-                             const Combine &cb, hipStream_t st)
+                             const Combine &cb, int shape, hipStream_t st)
 {
     if (g.dim != 2) return hipErrorInvalidValue;
-    if (g.npts >= (int64_t)128 * 1024) return tile2d_shape<32, 16>(g, sbp, ph, q, F, cb, st);
-    return tile2d_shape<16, 8>(g, sbp, ph, q, F, cb, st);
+    switch (shape) {
+    case 0: return tile2d_shape<32, 16, 1>(g, sbp, ph, q, F, cb, st);
+    case 1: return tile2d_shape<16, 8, 1>(g, sbp, ph, q, F, cb, st);
+    case 2: return tile2d_shape<16, 8, 2>(g, sbp, ph, q, F, cb, st);
+    case 3: return tile2d_shape<16, 8, 4>(g, sbp, ph, q, F, cb, st);
+    case 4: return tile2d_shape<32, 8, 1>(g, sbp, ph, q, F, cb, st);
+    case 5: return tile2d_shape<32, 8, 2>(g, sbp, ph, q, F, cb, st);
+    case 6: return tile2d_shape<16, 16, 1>(g, sbp, ph, q, F, cb, st);
+    case 7: return tile2d_shape<16, 16, 2>(g, sbp, ph, q, F, cb, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 #define DISPATCH_GRAD(DIM, SBP, CART) \

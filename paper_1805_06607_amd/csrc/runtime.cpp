@@ -44,6 +44,7 @@ struct GridHost {
     int32_t *recv_idx_d = nullptr;
     GridDev dev{};
     int head = 0;
+    int tile = -1;                    // 2D tile shape (-1: size-based default)
     // donor grid stepping slower than the fastest grid: its extrapolated
     // states at the points its donor stencils read, one buffer per mid-step
     std::vector<int32_t> closure;     // sorted donor-stencil points
@@ -455,7 +456,8 @@ int grid_rhs(mr_ctx *c, int gi, const double *q, double *F, const mrk::Combine &
     bool rec = timed && c->tgrid == gi && c->tcount < c->tmax;
     if (rec) HIPCHK(c, hipEventRecord(c->ev[2 * c->tcount], c->st));
     if (g.dim == 2 && !c->two_pass) {
-        HIPCHK(c, mrk::launch_rhs_tile2d(dev, c->P.sbp, c->ph, q, F, cb, c->st));
+        int shape = g.tile >= 0 ? g.tile : mrk::default_tile_shape(dev);
+        HIPCHK(c, mrk::launch_rhs_tile2d(dev, c->P.sbp, c->ph, q, F, cb, shape, c->st));
     } else {
         HIPCHK(c, mrk::launch_grad(dev, c->P.sbp, c->P.gamma - 1.0, q, g.grad, c->st));
         HIPCHK(c, mrk::launch_rhs(dev, c->grids_d + gi, c->P.sbp, c->ph, q, g.grad, F, cb, c->st));
@@ -967,6 +969,82 @@ int mr_kernel_time(mr_ctx *c, double *total_ms, int *count)
     *total_ms = tot;
     *count = c->tcount;
     return MR_OK;
+}
+
+int mr_set_option(mr_ctx *c, const char *name, int64_t value)
+{
+    if (!c || !name) return MR_ERR_ARG;
+    if (!strcmp(name, "rhs_two_pass")) {
+        if (value != 0 && value != 1) return fail(c, MR_ERR_ARG, "rhs_two_pass must be 0 or 1");
+        c->two_pass = value != 0;
+    } else {
+        return fail(c, MR_ERR_ARG, "unknown option '%s'", name);
+    }
+    return MR_OK;
+}
+
+int mr_set_tile_shape(mr_ctx *c, int g, int shape)
+{
+    if (!c || g < 0 || g >= (int)c->G.size() || shape < -1 || shape >= mrk::NUM_TILE_SHAPES) return MR_ERR_ARG;
+    if (c->G[g].dim != 2) return fail(c, MR_ERR_UNSUPPORTED, "tile shapes apply to 2D grids");
+    c->G[g].tile = shape;
+    return MR_OK;
+}
+
+int mr_get_tile_shape(const mr_ctx *c, int g, int *shape, int *tx, int *ty, int *tm)
+{
+    if (!c || !shape || g < 0 || g >= (int)c->G.size()) return MR_ERR_ARG;
+    const GridHost &G = c->G[g];
+    int s = G.dim != 2 ? -1 : G.tile >= 0 ? G.tile : mrk::default_tile_shape(G.dev);
+    *shape = s;
+    const mrk::TileShape z{0, 0, 0};
+    const mrk::TileShape &t = s >= 0 ? mrk::kTileShapes[s] : z;
+    if (tx) *tx = t.tx;
+    if (ty) *ty = t.ty;
+    if (tm) *tm = t.tm;
+    return MR_OK;
+}
+
+int mr_autotune(mr_ctx *c, int reps)
+{
+    if (!c || reps < 1 || reps > 1000) return MR_ERR_ARG;
+    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_autotune before mr_bind_workspace");
+    if (c->two_pass) return MR_OK;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    int rc = MR_OK;
+    for (size_t gi = 0; gi < c->G.size() && rc == MR_OK; ++gi) {
+        GridHost &g = c->G[gi];
+        if (g.dim != 2) continue;
+        // time the fused step (right-hand side and an AB combination) of the
+        // current state into the bootstrap scratch buffers
+        mrk::Combine cb{};
+        cb.m = c->P.hist_len;
+        for (int j = 0; j < cb.m - 1; ++j) { cb.c[j] = 0.0; cb.hist[j] = slot(c, g, j); }
+        cb.c[cb.m - 1] = 0.0;
+        cb.y_next = g.rk[1];
+        GridDev dev = g.dev;
+        dev.recv = recv_slice(c, g, 1);
+        double best = INFINITY;
+        int pick = mrk::default_tile_shape(dev);
+        for (int s = 0; s < mrk::NUM_TILE_SHAPES; ++s) {
+            hipError_t e = mrk::launch_rhs_tile2d(dev, c->P.sbp, c->ph, g.y[g.cur], g.rk[0], cb, s, c->st);
+            if (e == hipSuccess) e = hipEventRecord(e0, c->st);
+            for (int r = 0; r < reps && e == hipSuccess; ++r)
+                e = mrk::launch_rhs_tile2d(dev, c->P.sbp, c->ph, g.y[g.cur], g.rk[0], cb, s, c->st);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { rc = fail(c, MR_ERR_HIP, hipGetErrorString(e)); break; }
+            if (ms < best) { best = ms; pick = s; }
+        }
+        g.tile = pick;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 int mr_guard(mr_ctx *c, double *maxabs)

@@ -196,6 +196,26 @@ class System:
         self._check(self.lib.mr_kernel_time(self.ctx, byref(ms), byref(n)), "mr_kernel_time")
         return ms.value, n.value
 
+    def set_option(self, name: str, value: int):
+        """Launch-plan option ("rhs_two_pass")."""
+        self._check(self.lib.mr_set_option(self.ctx, name.encode(), int(value)), "mr_set_option")
+
+    def set_tile_shape(self, grid: int, shape: int):
+        """Tile shape of a 2D grid's fused kernel (-1: size-based default)."""
+        self._check(self.lib.mr_set_tile_shape(self.ctx, grid, shape), "mr_set_tile_shape")
+
+    def tile_shape(self, grid: int):
+        """(shape, tx, ty, tm) in use for a grid; shape -1 for 3D grids."""
+        s, tx, ty, tm = c_int(), c_int(), c_int(), c_int()
+        self._check(self.lib.mr_get_tile_shape(self.ctx, grid, byref(s), byref(tx), byref(ty), byref(tm)),
+                    "mr_get_tile_shape")
+        return s.value, tx.value, ty.value, tm.value
+
+    def autotune(self, reps: int = 20):
+        """Time every tile shape on each 2D grid and keep the fastest."""
+        self._check(self.lib.mr_autotune(self.ctx, reps), "mr_autotune")
+        return [self.tile_shape(g) for g in range(self.ngrids)]
+
     def close(self):
         if self.ctx:
             self.lib.mr_destroy(self.ctx)
