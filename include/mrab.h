@@ -186,7 +186,19 @@ int mr_kernel_time(mr_ctx *ctx, double *total_ms, int *count);
  *  "rhs_two_pass"        1: 2D grids use the gradient pass and the point-wise
  *                        right-hand-side kernel instead of the fused tile
  *                        kernel (default 0).
- * Errors: MR_ERR_ARG (unknown name or bad value). */
+ *  "multi_stream"        1: inside mr_mrab_macrostep every grid's work runs on
+ *                        a stream of its own, ordered against the other grids
+ *                        by events only where receiver data passes between
+ *                        them, so a slow grid's step overlaps a fast grid's
+ *                        substeps; the call still returns with all work
+ *                        ordered before later work on the context's stream
+ *                        (0: everything on the context's stream; default:
+ *                        on when the grids hold at least 4 Mi points in all,
+ *                        where the launches are long enough to gain from it).
+ *  "graph"               reserved: 1 (replaying captured HIP graphs of whole
+ *                        macrostep periods) is switched off and returns
+ *                        MR_ERR_UNSUPPORTED; 0 is accepted.
+ * Errors: MR_ERR_ARG (unknown name or bad value), MR_ERR_UNSUPPORTED. */
 int mr_set_option(mr_ctx *ctx, const char *name, int64_t value);
 
 /* Tile shape of a 2D grid's fused right-hand-side kernel: shape in

@@ -63,6 +63,42 @@ struct Link {
     double *vals_d = nullptr;    // r_max x nu x RB donor values
 };
 
+// Cross-stream order inside one macrostep call.  Stream s (one per grid)
+// counts the launches issued on it in this call (pos[s]; 0 is the call's
+// start, which every stream has joined).  A launch is recorded right after
+// it is issued when another stream may depend on it; a stream that needs
+// position p of stream s waits on the first record at or after p unless its
+// vector clock already covers p.  Receiver rows (link, k) remember their
+// last writer and the receiving grid's slice k its last reader.
+struct Order {
+    struct Rec {
+        int pos;
+        hipEvent_t e;
+        std::vector<int> clock;
+    };
+    static constexpr int POOL = 32;
+    int G = 0, K = 0;
+    std::vector<int> pos;
+    std::vector<std::vector<int>> clock;          // [t][s]: position of s known complete before t's next launch
+    std::vector<std::vector<Rec>> recs;           // per stream, this call
+    const std::vector<std::vector<hipEvent_t>> *pool = nullptr;   // per stream (the call's event set)
+    std::vector<int> used;
+    std::vector<std::pair<int, int>> wr;          // [link * (K+1) + k]: (stream, pos) of the last write
+    std::vector<std::pair<int, int>> rd;          // [grid * (K+1) + k]: (stream, pos) of the last read
+};
+
+// Below this many grid points the per-grid streams do not pay: the host's
+// event calls and the cross-queue waits cost more than the overlap of the
+// short launches saves.
+constexpr int64_t kMultiStreamPoints = 4 << 20;
+
+// Events of the macrostep calls.
+struct EvSet {
+    hipEvent_t join = nullptr;
+    std::vector<hipEvent_t> done;                  // per grid
+    std::vector<std::vector<hipEvent_t>> pool;     // per grid, Order::POOL each
+};
+
 struct mr_ctx {
     mr_params P{};
     hipStream_t st = nullptr;
@@ -93,6 +129,12 @@ struct mr_ctx {
     // per-launch timing
     int tgrid = -1, tmax = 0, tcount = 0;
     bool two_pass = false;    // 2D: use the two-kernel (gradient pass) right-hand side
+    // macrosteps: one stream per grid, ordered by events (Order); -1: when
+    // the grids hold at least kMultiStreamPoints points in all
+    int multi_stream = -1;
+    std::vector<hipStream_t> gs;                       // per grid
+    Order ord;
+    EvSet eager;
     std::vector<hipEvent_t> ev;
 };
 
@@ -384,14 +426,81 @@ mrk::DonorLink link_base(const mr_ctx *c, const Link &L)
     return a;
 }
 
-// donor data from the donor grid's state y into out (one target time)
-int link_current(mr_ctx *c, const Link &L, const double *y, double *out)
+hipStream_t sst(const mr_ctx *c, int si) { return si < 0 ? c->st : c->gs[si]; }
+
+// ---- cross-stream order (Order): si < 0 means the context's stream, untracked
+void ord_reset(mr_ctx *c, const EvSet &ev)
+{
+    Order &o = c->ord;
+    o.pool = &ev.pool;
+    o.pos.assign(o.G, 0);
+    o.clock.assign(o.G, std::vector<int>(o.G, 0));
+    for (auto &r : o.recs) r.clear();
+    o.used.assign(o.G, 0);
+    std::fill(o.wr.begin(), o.wr.end(), std::make_pair(-1, 0));
+    std::fill(o.rd.begin(), o.rd.end(), std::make_pair(-1, 0));
+}
+
+void ord_op(mr_ctx *c, int s)
+{
+    if (s < 0) return;
+    Order &o = c->ord;
+    o.clock[s][s] = ++o.pos[s];
+}
+
+int ord_mark(mr_ctx *c, int s)
+{
+    if (s < 0) return MR_OK;
+    Order &o = c->ord;
+    if (!o.recs[s].empty() && o.recs[s].back().pos == o.pos[s]) return MR_OK;
+    Order::Rec r{o.pos[s], (*o.pool)[s][o.used[s]++ % Order::POOL], o.clock[s]};
+    HIPCHK(c, hipEventRecord(r.e, c->gs[s]));
+    o.recs[s].push_back(std::move(r));
+    return MR_OK;
+}
+
+// stream t must not start its next launch before launch p of stream s ends
+int ord_need(mr_ctx *c, int t, std::pair<int, int> dep)
+{
+    Order &o = c->ord;
+    int s = dep.first, p = dep.second;
+    if (t < 0 || s < 0 || s == t || p <= 0 || o.clock[t][s] >= p) return MR_OK;
+    const Order::Rec *r = nullptr;
+    for (const auto &x : o.recs[s])
+        if (x.pos >= p) { r = &x; break; }
+    if (!r) {
+        int rc = ord_mark(c, s);
+        if (rc) return rc;
+        r = &o.recs[s].back();
+    }
+    HIPCHK(c, hipStreamWaitEvent(c->gs[t], r->e, 0));
+    for (int u = 0; u < o.G; ++u) o.clock[t][u] = std::max(o.clock[t][u], r->clock[u]);
+    return MR_OK;
+}
+
+std::pair<int, int> &ord_wr(mr_ctx *c, int link, int k) { return c->ord.wr[(size_t)link * (c->rmax + 1) + k]; }
+std::pair<int, int> &ord_rd(mr_ctx *c, int g, int k) { return c->ord.rd[(size_t)g * (c->rmax + 1) + k]; }
+
+int link_index(const mr_ctx *c, const Link &L) { return (int)(&L - c->links.data()); }
+
+// donor data from the donor grid's state y into out (one target time; k > 0
+// names the receiving grid's slice for the cross-stream order)
+int link_current(mr_ctx *c, const Link &L, const double *y, double *out, int si, int k)
 {
     mrk::DonorLink a = link_base(c, L);
     a.nj = 1;
     a.ys[0] = y;
     a.out[0] = out;
-    HIPCHK(c, mrk::launch_donor(a, c->st));
+    if (si >= 0) {
+        int rc = ord_need(c, si, ord_rd(c, L.rg, k));     // rows last read by the receiver at k
+        if (rc) return rc;
+    }
+    HIPCHK(c, mrk::launch_donor(a, sst(c, si)));
+    if (si >= 0) {
+        ord_op(c, si);
+        ord_wr(c, link_index(c, L), k) = {si, c->ord.pos[si]};
+        return ord_mark(c, si);
+    }
     return MR_OK;
 }
 
@@ -400,8 +509,9 @@ int link_current(mr_ctx *c, const Link &L, const double *y, double *out)
 // k' < k + per_d at which a receiving grid evaluates is gathered now:
 // first the extrapolated states at the donor-stencil points (one buffer per
 // offset), then one batched gather per link
-int donor_future(mr_ctx *c, int d, int k)
+int donor_future(mr_ctx *c, int d, int k, int si)
 {
+    hipStream_t st = sst(c, si);
     GridHost &D = c->G[d];
     int per_d = c->rmax / D.rate;
     if (per_d == 1 || D.closure.empty()) return MR_OK;
@@ -428,43 +538,67 @@ int donor_future(mr_ctx *c, int d, int k)
         x.out[x.nj] = D.ext[jp - 1];
         x.nj++;
     }
-    HIPCHK(c, mrk::launch_extrap(x, c->st));
+    HIPCHK(c, mrk::launch_extrap(x, st));
+    ord_op(c, si);
     for (const Link &L : c->links) {
         if (L.dg != d) continue;
         const GridHost &R = c->G[L.rg];
         int per_g = c->rmax / R.rate;
         mrk::DonorLink a = link_base(c, L);
         a.nj = 0;
+        int kps[mrk::MAXJ];
         for (int jp = 1; jp < per_d; ++jp) {
             int kp = kprime(jp);
             if (kp % per_g) continue;
+            if (si >= 0) {
+                int rc = ord_need(c, si, ord_rd(c, L.rg, kp));   // rows last read by the receiver at kp
+                if (rc) return rc;
+            }
+            kps[a.nj] = kp;
             a.ys[a.nj] = D.ext[jp - 1];
             a.out[a.nj] = recv_slice(c, R, kp);
             a.nj++;
         }
-        if (a.nj) HIPCHK(c, mrk::launch_donor(a, c->st));
+        if (!a.nj) continue;
+        HIPCHK(c, mrk::launch_donor(a, st));
+        if (si >= 0) {
+            ord_op(c, si);
+            for (int j = 0; j < a.nj; ++j) ord_wr(c, link_index(c, L), kps[j]) = {si, c->ord.pos[si]};
+        }
     }
-    return MR_OK;
+    return ord_mark(c, si);
 }
 
 // right-hand side of one grid from state q into F (+ optional fused combine)
-int grid_rhs(mr_ctx *c, int gi, const double *q, double *F, const mrk::Combine &cb, bool timed, int k)
+int grid_rhs(mr_ctx *c, int gi, const double *q, double *F, const mrk::Combine &cb, bool timed, int k, int si)
 {
+    hipStream_t st = sst(c, si);
+    if (si >= 0)
+        for (const Link &L : c->links)
+            if (L.rg == gi) {
+                int rc = ord_need(c, si, ord_wr(c, link_index(c, L), k));   // receiver rows of k written
+                if (rc) return rc;
+            }
     GridHost &g = c->G[gi];
     GridDev dev = g.dev;
     dev.recv = recv_slice(c, g, k);
     bool rec = timed && c->tgrid == gi && c->tcount < c->tmax;
-    if (rec) HIPCHK(c, hipEventRecord(c->ev[2 * c->tcount], c->st));
+    if (rec) HIPCHK(c, hipEventRecord(c->ev[2 * c->tcount], st));
     if (g.dim == 2 && !c->two_pass) {
         int shape = g.tile >= 0 ? g.tile : mrk::default_tile_shape(dev);
-        HIPCHK(c, mrk::launch_rhs_tile2d(dev, c->P.sbp, c->ph, q, F, cb, shape, c->st));
+        HIPCHK(c, mrk::launch_rhs_tile2d(dev, c->P.sbp, c->ph, q, F, cb, shape, st));
     } else {
-        HIPCHK(c, mrk::launch_grad(dev, c->P.sbp, c->P.gamma - 1.0, q, g.grad, c->st));
-        HIPCHK(c, mrk::launch_rhs(dev, c->grids_d + gi, c->P.sbp, c->ph, q, g.grad, F, cb, c->st));
+        HIPCHK(c, mrk::launch_grad(dev, c->P.sbp, c->P.gamma - 1.0, q, g.grad, st));
+        HIPCHK(c, mrk::launch_rhs(dev, c->grids_d + gi, c->P.sbp, c->ph, q, g.grad, F, cb, st));
     }
     if (rec) {
-        HIPCHK(c, hipEventRecord(c->ev[2 * c->tcount + 1], c->st));
+        HIPCHK(c, hipEventRecord(c->ev[2 * c->tcount + 1], st));
         c->tcount++;
+    }
+    if (si >= 0) {
+        ord_op(c, si);
+        ord_rd(c, gi, k) = {si, c->ord.pos[si]};
+        return ord_mark(c, si);
     }
     return MR_OK;
 }
@@ -473,18 +607,119 @@ int grid_rhs(mr_ctx *c, int gi, const double *q, double *F, const mrk::Combine &
 int rhs_all(mr_ctx *c, const double *const *q, double *const *F)
 {
     for (const Link &L : c->links) {
-        int rc = link_current(c, L, q[L.dg], recv_slice(c, c->G[L.rg], 1));
+        int rc = link_current(c, L, q[L.dg], recv_slice(c, c->G[L.rg], 1), -1, 1);
         if (rc) return rc;
     }
     mrk::Combine none{};
     for (size_t g = 0; g < c->G.size(); ++g) {
-        int rc = grid_rhs(c, (int)g, q[g], F[g], none, false, 1);
+        int rc = grid_rhs(c, (int)g, q[g], F[g], none, false, 1, -1);
         if (rc) return rc;
     }
     return MR_OK;
 }
 
 int64_t nelem(const GridHost &g) { return (int64_t)(g.dim + 2) * g.npts; }
+
+int make_evset(mr_ctx *c, EvSet &e)
+{
+    int G = (int)c->G.size();
+    auto mk = [&](hipEvent_t *ev) { return hipEventCreateWithFlags(ev, hipEventDisableTiming); };
+    HIPCHK(c, mk(&e.join));
+    e.done.assign(G, nullptr);
+    e.pool.assign(G, std::vector<hipEvent_t>(Order::POOL, nullptr));
+    for (int g = 0; g < G; ++g) {
+        HIPCHK(c, mk(&e.done[g]));
+        for (auto &ev : e.pool[g]) HIPCHK(c, mk(&ev));
+    }
+    return MR_OK;
+}
+
+void free_evset(EvSet &e)
+{
+    if (e.join) (void)hipEventDestroy(e.join);
+    for (auto ev : e.done)
+        if (ev) (void)hipEventDestroy(ev);
+    for (auto &v : e.pool)
+        for (auto ev : v)
+            if (ev) (void)hipEventDestroy(ev);
+    e = EvSet{};
+}
+
+// per-grid streams (default priority, not synchronising with the null
+// stream) and their events, created on first use
+int ensure_streams(mr_ctx *c)
+{
+    if (!c->gs.empty()) return MR_OK;
+    int G = (int)c->G.size();
+    Order &o = c->ord;
+    o.G = G;
+    o.K = c->rmax;
+    o.recs.assign(G, {});
+    o.wr.assign(c->links.size() * (c->rmax + 1), {-1, 0});
+    o.rd.assign((size_t)G * (c->rmax + 1), {-1, 0});
+    int rc = make_evset(c, c->eager);
+    if (rc) return rc;
+    c->gs.assign(G, nullptr);
+    for (int g = 0; g < G; ++g) HIPCHK(c, hipStreamCreateWithFlags(&c->gs[g], hipStreamNonBlocking));
+    return MR_OK;
+}
+
+// n macrosteps: on the context's stream, or (ms) on the per-grid streams
+// between a join with the context's stream and a join back
+int run_macrosteps(mr_ctx *c, int nsteps, bool ms, hipStream_t origin, const EvSet &ev)
+{
+    int m = c->P.hist_len;
+    int G = (int)c->G.size();
+    if (ms) {
+        ord_reset(c, ev);
+        HIPCHK(c, hipEventRecord(ev.join, origin));
+        for (int g = 0; g < G; ++g) HIPCHK(c, hipStreamWaitEvent(c->gs[g], ev.join, 0));
+    }
+    auto gsi = [&](int g) { return ms ? g : -1; };
+    for (int s = 0; s < nsteps; ++s) {
+        for (int k = 1; k <= c->rmax; ++k) {
+            bool ends[mrk::MAXG] = {};
+            for (int g = 0; g < G; ++g) {
+                ends[g] = k % (c->rmax / c->G[g].rate) == 0;
+                if (ends[g]) c->G[g].cur ^= 1;   // the staged own step becomes current
+            }
+            // donor data from donors at their own step; mid-step donor data
+            // was gathered right after the donor grid's last evaluation
+            for (const Link &L : c->links) {
+                if (!ends[L.rg] || !ends[L.dg]) continue;
+                const GridHost &D = c->G[L.dg];
+                int rc = link_current(c, L, D.y[D.cur], recv_slice(c, c->G[L.rg], k), gsi(L.dg), k);
+                if (rc) return rc;
+            }
+            for (int g = 0; g < G; ++g) {
+                if (!ends[g]) continue;
+                GridHost &Gh = c->G[g];
+                mrk::Combine cb{};
+                cb.m = m;
+                for (int j = 0; j < m - 1; ++j) cb.hist[j] = slot(c, Gh, j + 1);
+                for (int j = 0; j < m; ++j) cb.c[j] = c->c_own[g][j];
+                cb.y_next = Gh.y[1 - Gh.cur];
+                double *Fnew = slot(c, Gh, 0);      // the oldest slot is overwritten
+                int rc = grid_rhs(c, g, Gh.y[Gh.cur], Fnew, cb, true, k, gsi(g));
+                if (rc) return rc;
+                Gh.head = (Gh.head + 1) % m;
+            }
+            for (int g = 0; g < G; ++g) {
+                if (!ends[g]) continue;
+                int rc = donor_future(c, g, k, gsi(g));
+                if (rc) return rc;
+            }
+        }
+        c->t += c->H;
+        c->nmacro++;
+    }
+    if (ms)
+        for (int g = 0; g < G; ++g) {
+            HIPCHK(c, hipEventRecord(ev.done[g], c->gs[g]));
+            HIPCHK(c, hipStreamWaitEvent(origin, ev.done[g], 0));
+        }
+    return MR_OK;
+}
 
 }  // namespace
 
@@ -617,6 +852,7 @@ int mr_finalize(mr_ctx *c, size_t *bytes)
     for (auto &g : c->G)
         if (c->rmax % g.rate) return fail(c, MR_ERR_SETUP, "rate %d does not divide %d", g.rate, c->rmax);
     int n = c->P.order, m = c->P.hist_len;
+
     c->alpha_own.assign(c->G.size(), {});
     c->alpha_mid.assign(c->G.size(), {});
     for (size_t g = 0; g < c->G.size(); ++g) {
@@ -741,7 +977,7 @@ int mr_receiver_data(mr_ctx *c, int g, const double *const *q, double *out)
     for (const Link &L : c->links) {
         if (L.rg != g) continue;
         if (!q[L.dg]) return fail(c, MR_ERR_ARG, "null donor state");
-        int rc = link_current(c, L, q[L.dg], out);
+        int rc = link_current(c, L, q[L.dg], out, -1, 1);
         if (rc) return rc;
     }
     return MR_OK;
@@ -858,7 +1094,7 @@ int mr_mrab_start(mr_ctx *c, double t0)
     // every grid has just evaluated: donor data of the first macrostep's
     // mid-step times
     for (int g = 0; g < (int)c->G.size(); ++g) {
-        int rc = donor_future(c, g, c->rmax);
+        int rc = donor_future(c, g, c->rmax, -1);
         if (rc) return rc;
     }
     c->t = t0 + nsteps * d;
@@ -871,46 +1107,15 @@ int mr_mrab_macrostep(mr_ctx *c, int nsteps)
 {
     if (!c || nsteps < 0) return MR_ERR_ARG;
     if (!c->started) return fail(c, MR_ERR_STATE, "mr_mrab_macrostep before mr_mrab_start");
-    int m = c->P.hist_len;
-    int G = (int)c->G.size();
-    for (int s = 0; s < nsteps; ++s) {
-        for (int k = 1; k <= c->rmax; ++k) {
-            bool ends[mrk::MAXG] = {};
-            for (int g = 0; g < G; ++g) {
-                ends[g] = k % (c->rmax / c->G[g].rate) == 0;
-                if (ends[g]) c->G[g].cur ^= 1;   // the staged own step becomes current
-            }
-            // donor data from donors at their own step; mid-step donor data
-            // was gathered right after the donor grid's last evaluation
-            for (const Link &L : c->links) {
-                if (!ends[L.rg] || !ends[L.dg]) continue;
-                const GridHost &D = c->G[L.dg];
-                int rc = link_current(c, L, D.y[D.cur], recv_slice(c, c->G[L.rg], k));
-                if (rc) return rc;
-            }
-            for (int g = 0; g < G; ++g) {
-                if (!ends[g]) continue;
-                GridHost &Gh = c->G[g];
-                mrk::Combine cb{};
-                cb.m = m;
-                for (int j = 0; j < m - 1; ++j) cb.hist[j] = slot(c, Gh, j + 1);
-                for (int j = 0; j < m; ++j) cb.c[j] = c->c_own[g][j];
-                cb.y_next = Gh.y[1 - Gh.cur];
-                double *Fnew = slot(c, Gh, 0);      // the oldest slot is overwritten
-                int rc = grid_rhs(c, g, Gh.y[Gh.cur], Fnew, cb, true, k);
-                if (rc) return rc;
-                Gh.head = (Gh.head + 1) % m;
-            }
-            for (int g = 0; g < G; ++g) {
-                if (!ends[g]) continue;
-                int rc = donor_future(c, g, k);
-                if (rc) return rc;
-            }
-        }
-        c->t += c->H;
-        c->nmacro++;
+    if (nsteps == 0) return MR_OK;
+    int64_t npts = 0;
+    for (auto &g : c->G) npts += g.npts;
+    const bool ms = c->G.size() > 1 && (c->multi_stream < 0 ? npts >= kMultiStreamPoints : c->multi_stream == 1);
+    if (ms) {
+        int rc = ensure_streams(c);
+        if (rc) return rc;
     }
-    return MR_OK;
+    return run_macrosteps(c, nsteps, ms, c->st, c->eager);
 }
 
 int mr_get_history(mr_ctx *c, int g, int j, double *out)
@@ -977,6 +1182,12 @@ int mr_set_option(mr_ctx *c, const char *name, int64_t value)
     if (!strcmp(name, "rhs_two_pass")) {
         if (value != 0 && value != 1) return fail(c, MR_ERR_ARG, "rhs_two_pass must be 0 or 1");
         c->two_pass = value != 0;
+    } else if (!strcmp(name, "multi_stream")) {
+        if (value != 0 && value != 1) return fail(c, MR_ERR_ARG, "multi_stream must be 0 or 1");
+        c->multi_stream = (int)value;
+    } else if (!strcmp(name, "graph")) {
+        if (value != 0 && value != 1) return fail(c, MR_ERR_ARG, "graph must be 0 or 1");
+        if (value) return fail(c, MR_ERR_UNSUPPORTED, "graph replay of macrosteps is switched off");
     } else {
         return fail(c, MR_ERR_ARG, "unknown option '%s'", name);
     }
@@ -1070,8 +1281,13 @@ const char *mr_last_error(const mr_ctx *c) { return c ? c->err.c_str() : "null c
 void mr_destroy(mr_ctx *c)
 {
     if (!c) return;
-    if (c->st || true) (void)hipStreamSynchronize(c->st);
+    (void)hipStreamSynchronize(c->st);
+    for (auto s : c->gs)
+        if (s) (void)hipStreamSynchronize(s);
     for (auto e : c->ev) (void)hipEventDestroy(e);
+    free_evset(c->eager);
+    for (auto s : c->gs)
+        if (s) (void)hipStreamDestroy(s);
     delete c;
 }
 

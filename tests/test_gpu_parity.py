@@ -230,3 +230,54 @@ def test_tile_shapes_agree(torch):
             e = rel_l2(out[g], ref[g])
             _say("cylinder_small shape", shape, g, e)
             assert np.all(e <= 1e-12), (shape, g, e)
+
+
+@pytest.mark.parametrize("case", ["vortex_box", "cylinder_small"])
+def test_multi_stream_bitwise(torch, case):
+    """Per-grid streams ordered by events give the same bits as every launch
+    in order on one stream.  The calls mix lengths, with host reads and
+    synchronisation between them; every call's result is compared."""
+    from paper_1805_06607_amd.system import System
+    plans = {"one_stream": {"multi_stream": 0}, "streams": {"multi_stream": 1}}
+    systems = {}
+    for name, opts in plans.items():
+        wl = CASES[case]()
+        s = System(wl)
+        for o, v in opts.items():
+            s.set_option(o, v)
+        s.timestep()
+        s.start(0.0)
+        systems[name] = s
+    ng = len(wl.grids)
+    m = wl.params["hist_len"]
+    for n in (1, 7, 12, 5, 6, 13, 24):
+        snap = {}
+        for name, s in systems.items():
+            s.macrostep(n)
+            torch.cuda.synchronize()
+            snap[name] = [s.state(g).clone() for g in range(ng)] + \
+                [s.history(g, j).clone() for g in range(ng) for j in range(m)]
+        for a, b in zip(snap["one_stream"], snap["streams"]):
+            assert torch.equal(a, b), (case, n)
+        t = [s.time() for s in systems.values()]
+        assert t[0] == t[1], t
+
+
+@pytest.mark.skip(reason="graph replay of captured macrosteps is switched off: both runs of the "
+                         "capture path ended the process with a segmentation fault inside the HIP "
+                         "runtime; cause not found")
+def test_graph_replay_bitwise(torch):
+    from paper_1805_06607_amd.system import System
+    wl = CASES["cylinder_small"]()
+    ref, s = System(wl), System(CASES["cylinder_small"]())
+    ref.set_option("multi_stream", 0)
+    s.set_option("graph", 1)
+    for x in (ref, s):
+        x.timestep()
+        x.start(0.0)
+    for n in (1, 7, 12, 5):
+        ref.macrostep(n)
+        s.macrostep(n)
+        torch.cuda.synchronize()
+        for g in range(2):
+            assert torch.equal(ref.state(g), s.state(g)), (n, g)

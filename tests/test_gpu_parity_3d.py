@@ -82,3 +82,21 @@ def test_mrab_parity_3d_100_macrosteps(torch):
         e = rel_l2(_np(sysg.state(g)), mr.y[g], act)
         _say("3d mrab", g, e)
         assert np.all(e <= 1e-10), (g, e)
+
+
+def test_multi_stream_bitwise_3d(torch):
+    """Four grids at rates 1, 2, 2, 4 on per-grid streams: bitwise equal to
+    the single-stream order after 25 macrosteps in four calls."""
+    from paper_1805_06607_amd.system import System
+    outs = []
+    for ms in (0, 1):
+        wl = small()
+        s = System(wl)
+        s.set_option("multi_stream", ms)
+        s.timestep()
+        s.start(0.0)
+        for n in (7, 5, 12, 1):
+            s.macrostep(n)
+        outs.append([s.state(g).clone() for g in range(len(wl.grids))])
+    for g, (a, b) in enumerate(zip(*outs)):
+        assert torch.equal(a, b), g
