@@ -17,9 +17,11 @@ value = MRAB point-updates per second = sum_l r_l * N_l(active) * K / time.
 
 Also reported: the single-rate AB (every grid at the fast step) rate, the
 errors of both against a single-rate reference at a 4x smaller step (equal
-error check), the roofline of the dominant kernel (the background grid's
-right-hand-side step, timed with HIP events on the library's stream inside
-the timed region), and the CPU oracle on a bounded sample.
+error check), the roofline of the dominant kernel (the fused right-hand-side
+step of every grid, each launch timed with HIP events on the stream it runs on
+inside the timed region; HBM traffic per launch from the committed counter
+summary when it matches the kernels' source), and the CPU oracle on a bounded
+sample.
 """
 import argparse
 import json
@@ -61,29 +63,106 @@ def run_tgv3d(args):
     n_act = active_counts(s)
     pts = sum(g.rate * n for g, n in zip(wl.grids, n_act))
     s.macrostep(args.warmup)
-    s.kernel_timing(0, args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.macrostep(args.steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    ktot, kc = s.kernel_time()
     s.guard()
-    bpp = bytes_per_point(wl, 0)
-    per_launch = n_act[0] * bpp
-    avg = ktot / max(kc, 1) * 1e-3
-    ach = per_launch / avg / 1e9
+    # launch durations from a single-stream pass (on the per-grid streams the
+    # grids' launches overlap and each event pair would also time the others)
+    s.set_option("multi_stream", 0)
+    roof = timed_pass(s, wl, n_act, args.steps, "gradient pass + point-wise right-hand side with fused AB "
+                                                "update (k_grad + k_rhs), all grids' launches of a macrostep")
     line = {"metric": "MRAB pt-updates/s (3D three-level case), 1 GPU", "value": pts * args.steps / el,
             "unit": "pt-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
             "config": {"workload": "3D periodic 192^3 + 2 x 96^3 (half spacing) + 64^3 (quarter spacing), "
                                    "SBP 4-2, cubic donors, AB3, rates 1/2/2/4, Re 1600, M 0.3",
                        "points_active": n_act, "H": H},
-            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                         "kernel": "background-grid right-hand-side step", "bytes_per_launch": per_launch,
-                         "bytes_per_point": bpp, "avg_launch_us": avg * 1e6, "launches_timed": kc}}
+            "roofline": roof}
     print(json.dumps(line), flush=True)
+
+
+def kernel_names(sysg, wl):
+    """Kernel instantiation of each grid's fused 2D right-hand side."""
+    names = []
+    for g, gr in enumerate(wl.grids):
+        shape, tx, ty, tm = sysg.tile_shape(g)
+        if shape < 0:
+            names.append(None)
+            continue
+        names.append(f"k_rhs_tile2d<{int(wl.params['sbp'])}, {0 if gr.kind == 1 else 1}, {tx}, {ty}, {tm}>")
+    return names
+
+
+def stored_traffic():
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the kernels as they are now (same source hash)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    src = os.path.join(ROOT, "paper_1805_06607_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return {}
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    out, ok = {}, False
+    with open(path) as f:
+        for ln in f:
+            ln = ln.strip()
+            if ln.startswith("kernels_sha256"):
+                ok = ln.split("=", 1)[1].strip() == sha
+            elif ln.startswith("k_") and "bytes_per_launch=" in ln:
+                name, val = ln.rsplit("bytes_per_launch=", 1)
+                out[name.split(" grid=")[0].strip()] = float(val)
+    return out if ok else {}
+
+
+def timed_pass(sysg, wl, n_act, steps, what):
+    """K more macrosteps with every fused right-hand-side launch between HIP
+    events on its stream; the roofline of those launches."""
+    import torch
+    sysg.kernel_timing(-2, steps * sum(g.rate for g in wl.grids))
+    sysg.macrostep(steps)
+    torch.cuda.synchronize()
+    out = roofline(sysg, wl, n_act, what)
+    sysg.kernel_timing(-1, 0)
+    return out
+
+
+def roofline(sysg, wl, n_act, what):
+    """Roofline of the fused right-hand-side step over every timed launch of
+    the timed region: algorithmic bytes (bytes_per_point x active points per
+    launch) / summed launch duration, and per grid."""
+    per_grid, tb, tt, tn = [], 0.0, 0.0, 0
+    names = kernel_names(sysg, wl) if wl.dim == 2 else [None] * len(wl.grids)
+    traffic = stored_traffic()
+    tr_bytes, tr_ok = 0.0, True
+    for g in range(len(wl.grids)):
+        ms, cnt = sysg.kernel_time(g)
+        if cnt == 0:
+            continue
+        bpp = bytes_per_point(wl, g)
+        bl = n_act[g] * bpp
+        avg = ms * 1e-3 / cnt
+        ach = bl / avg / 1e9
+        d = {"grid": g, "n": list(wl.grids[g].n), "kernel": names[g], "points": n_act[g], "bytes_per_point": bpp,
+             "bytes_per_launch": bl, "launches": cnt, "avg_launch_us": avg * 1e6, "achieved": ach,
+             "frac": ach / HBM_PEAK_GBS}
+        if names[g] in traffic:
+            d["traffic"] = traffic[names[g]]
+            tr_bytes += traffic[names[g]] * cnt
+        else:
+            tr_ok = False
+        per_grid.append(d)
+        tb += bl * cnt
+        tt += ms * 1e-3
+        tn += cnt
+    ach = tb / tt / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": (tr_bytes / tn) if (tr_ok and tn) else None, "kernel": what,
+            "bytes_per_launch": tb / tn, "avg_launch_us": tt / tn * 1e6, "launches_timed": tn,
+            "per_grid": per_grid}
 
 
 def active_counts(sysg):
@@ -114,34 +193,29 @@ def run_gpu(args):
     mr = System(wl)
     h, H = mr.timestep()
     mr.start(0.0)
+    tiles = mr.autotune(reps=20)
+    log(f"tile shapes (shape, tx, ty, threads per output): {tiles}")
     n_act = active_counts(mr)
     rates = [g.rate for g in wl.grids]
     pts_per_step = sum(r * n for r, n in zip(rates, n_act))
     mr.macrostep(args.warmup)
-    mr.kernel_timing(0, args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mr.macrostep(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dt_mrab = t1 - t0
-    ktot_ms, kcount = mr.kernel_time()
     mr.guard()
-    log(f"MRAB {args.steps} macrosteps: {dt_mrab * 1e3:.2f} ms, kernel {ktot_ms:.3f} ms over {kcount}")
-    res["mrab"] = dict(time_s=dt_mrab, pts_per_step=pts_per_step, H=H, h=h)
-    # roofline of the dominant kernel (background grid right-hand-side step)
-    bpp = bytes_per_point(wl, 0)
-    per_launch = n_act[0] * bpp
-    avg_s = (ktot_ms / max(kcount, 1)) * 1e-3
-    achieved = per_launch / avg_s / 1e9
-    res["roofline"] = {
-        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-        "kernel": "k_rhs_tile2d on the background grid (fused gradients, flux divergence, SAT, "
-                  "AB update)",
-        "bytes_per_launch": per_launch, "bytes_per_point": bpp, "points": n_act[0],
-        "avg_launch_us": avg_s * 1e6, "launches_timed": kcount,
-    }
+    log(f"MRAB {args.steps} macrosteps: {dt_mrab * 1e3:.2f} ms")
+    res["mrab"] = dict(time_s=dt_mrab, pts_per_step=pts_per_step, H=H, h=h, tiles=tiles)
+    # roofline of the dominant kernel: the fused right-hand-side step, every
+    # launch (1 background + 4 O-mesh per macrostep) of a second pass of K
+    # macrosteps identical to the timed one, each launch between HIP events
+    # (the events themselves cost host time, so the throughput above is taken
+    # without them)
+    res["roofline"] = timed_pass(mr, wl, n_act, args.steps,
+                                 "k_rhs_tile2d (fused gradients, flux divergence, SAT, AB update), "
+                                 "all launches of a macrostep (background and O-mesh)")
     del mr
     # ---------------------------------------------------------------- SRAB
     wls = workload((1, 1))
@@ -150,6 +224,7 @@ def run_gpu(args):
     sr = System(wls)
     sr.timestep()
     sr.start(0.0)
+    sr.autotune(reps=20)
     sr.macrostep(args.warmup)
     torch.cuda.synchronize()
     nsr = args.steps * 4
@@ -304,7 +379,7 @@ def main():
             "workload": "cylinder-like overset: 512x512 Cartesian background (far field, hole r<2) + "
                         "256x128 O-mesh (wall), SBP 4-2, cubic donors, AB4 MRAB ratio 4, Re 200, M 0.2",
             "points_active": n_act, "rates": [g.rate for g in wl.grids],
-            "H": res["mrab"]["H"], "h": res["mrab"]["h"],
+            "H": res["mrab"]["H"], "h": res["mrab"]["h"], "tile_shapes": res["mrab"]["tiles"],
         },
         "roofline": res["roofline"],
         "srab": {

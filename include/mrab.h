@@ -174,11 +174,15 @@ int mr_time(const mr_ctx *ctx, double *t, int64_t *macrosteps);
  * (eq. vandermonde; minimum norm when hist_len > order, eq. ext_ab). */
 int mr_ab_coeffs(int order, int hist_len, double tau, double *out);
 
-/* Per-launch timing of one grid's fused right-hand-side kernel with HIP events
- * recorded on the context's stream (max_events launches are recorded; 0
- * disables).  mr_kernel_time synchronises and returns the summed duration and
- * the number of timed launches since the last enable. */
+/* Per-launch timing of the grids' fused right-hand-side kernels with HIP
+ * events recorded on the stream each launch is issued on: grid >= 0 times that
+ * grid's launches, MR_ALL_GRIDS every grid's, -1 disables; at most max_events
+ * launches are recorded.  mr_kernel_time synchronises and returns the summed
+ * duration and the number of timed launches since the last enable;
+ * mr_kernel_time_grid the same for one grid's launches (-1: all). */
+enum { MR_ALL_GRIDS = -2 };
 int mr_kernel_timing(mr_ctx *ctx, int grid, int max_events);
+int mr_kernel_time_grid(mr_ctx *ctx, int grid, double *total_ms, int *count);
 int mr_kernel_time(mr_ctx *ctx, double *total_ms, int *count);
 
 /* Execution options (any time after mr_create; they change the launch plan,

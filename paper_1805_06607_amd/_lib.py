@@ -59,6 +59,7 @@ SIGNATURES = {
     "mr_ab_coeffs": [c_int, c_int, c_double, POINTER(c_double)],
     "mr_kernel_timing": [c_void_p, c_int, c_int],
     "mr_kernel_time": [c_void_p, POINTER(c_double), POINTER(c_int)],
+    "mr_kernel_time_grid": [c_void_p, c_int, POINTER(c_double), POINTER(c_int)],
     "mr_set_option": [c_void_p, c_char_p, c_int64],
     "mr_set_tile_shape": [c_void_p, c_int, c_int],
     "mr_get_tile_shape": [c_void_p, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_int)],

@@ -127,7 +127,8 @@ struct mr_ctx {
     double *partial = nullptr;
     mrk::Phys ph{};
     // per-launch timing
-    int tgrid = -1, tmax = 0, tcount = 0;
+    int tgrid = -1, tmax = 0, tcount = 0;    // tgrid -2: every grid
+    std::vector<int> tgrid_of;                // grid of each timed launch
     bool two_pass = false;    // 2D: use the two-kernel (gradient pass) right-hand side
     // macrosteps: one stream per grid, ordered by events (Order); -1: when
     // the grids hold at least kMultiStreamPoints points in all
@@ -582,7 +583,7 @@ int grid_rhs(mr_ctx *c, int gi, const double *q, double *F, const mrk::Combine &
     GridHost &g = c->G[gi];
     GridDev dev = g.dev;
     dev.recv = recv_slice(c, g, k);
-    bool rec = timed && c->tgrid == gi && c->tcount < c->tmax;
+    bool rec = timed && (c->tgrid == gi || c->tgrid == -2) && c->tcount < c->tmax;
     if (rec) HIPCHK(c, hipEventRecord(c->ev[2 * c->tcount], st));
     if (g.dim == 2 && !c->two_pass) {
         int shape = g.tile >= 0 ? g.tile : mrk::default_tile_shape(dev);
@@ -593,6 +594,7 @@ int grid_rhs(mr_ctx *c, int gi, const double *q, double *F, const mrk::Combine &
     }
     if (rec) {
         HIPCHK(c, hipEventRecord(c->ev[2 * c->tcount + 1], st));
+        c->tgrid_of[c->tcount] = gi;
         c->tcount++;
     }
     if (si >= 0) {
@@ -1146,13 +1148,14 @@ int mr_ab_coeffs(int order, int hist_len, double tau, double *out)
 
 int mr_kernel_timing(mr_ctx *c, int grid, int max_events)
 {
-    if (!c || grid < -1 || grid >= (int)c->G.size() || max_events < 0) return MR_ERR_ARG;
+    if (!c || grid < -2 || grid >= (int)c->G.size() || max_events < 0) return MR_ERR_ARG;
     HIPCHK(c, hipStreamSynchronize(c->st));
     for (auto e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
     c->tgrid = max_events ? grid : -1;
     c->tmax = max_events;
     c->tcount = 0;
+    c->tgrid_of.assign(max_events, -1);
     for (int i = 0; i < 2 * max_events; ++i) {
         hipEvent_t e;
         HIPCHK(c, hipEventCreate(&e));
@@ -1161,20 +1164,25 @@ int mr_kernel_timing(mr_ctx *c, int grid, int max_events)
     return MR_OK;
 }
 
-int mr_kernel_time(mr_ctx *c, double *total_ms, int *count)
+int mr_kernel_time_grid(mr_ctx *c, int grid, double *total_ms, int *count)
 {
-    if (!c || !total_ms || !count) return MR_ERR_ARG;
+    if (!c || !total_ms || !count || grid < -1 || grid >= (int)c->G.size()) return MR_ERR_ARG;
     HIPCHK(c, hipStreamSynchronize(c->st));
     double tot = 0;
+    int n = 0;
     for (int i = 0; i < c->tcount; ++i) {
+        if (grid >= 0 && c->tgrid_of[i] != grid) continue;
         float ms = 0;
         HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
         tot += ms;
+        n++;
     }
     *total_ms = tot;
-    *count = c->tcount;
+    *count = n;
     return MR_OK;
 }
+
+int mr_kernel_time(mr_ctx *c, double *total_ms, int *count) { return mr_kernel_time_grid(c, -1, total_ms, count); }
 
 int mr_set_option(mr_ctx *c, const char *name, int64_t value)
 {

@@ -189,11 +189,13 @@ class System:
         return v.value
 
     def kernel_timing(self, grid: int, max_events: int):
+        """Time the fused right-hand-side launches of one grid (-2: all grids)."""
         self._check(self.lib.mr_kernel_timing(self.ctx, grid, max_events), "mr_kernel_timing")
 
-    def kernel_time(self):
+    def kernel_time(self, grid: int = -1):
+        """(summed ms, launches) of the timed launches (grid -1: all grids)."""
         ms, n = c_double(), c_int()
-        self._check(self.lib.mr_kernel_time(self.ctx, byref(ms), byref(n)), "mr_kernel_time")
+        self._check(self.lib.mr_kernel_time_grid(self.ctx, grid, byref(ms), byref(n)), "mr_kernel_time_grid")
         return ms.value, n.value
 
     def set_option(self, name: str, value: int):
