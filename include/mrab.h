@@ -199,6 +199,13 @@ int mr_kernel_time(mr_ctx *ctx, double *total_ms, int *count);
  *                        (0: everything on the context's stream; default:
  *                        on when the grids hold at least 4 Mi points in all,
  *                        where the launches are long enough to gain from it).
+ *  "donor_blocks"        1: links with stencils of at most 16 entries whose
+ *                        receiver chunks fit one workgroup's LDS get their
+ *                        receiver rows in one launch per donor step (the
+ *                        extrapolant at the points the chunk reads, the values
+ *                        at its distinct donor points, the weighted sums);
+ *                        0: always the values-then-gather launches, with a
+ *                        separate extrapolation launch (default 1).
  *  "graph"               reserved: 1 (replaying captured HIP graphs of whole
  *                        macrostep periods) is switched off and returns
  *                        MR_ERR_UNSUPPORTED; 0 is accepted.

@@ -56,6 +56,9 @@ struct DonorLink {
     int nj;
     const double *ys[MAXJ];
     double *out[MAXJ];
+    int m;                     // block launch: extrapolant ys[j] + sum_h beta[j][h] hist[h] when m > 0
+    double beta[MAXJ][MAXH];
+    const double *hist[MAXH];
     double *vals;              // nj x nu x RB scratch
     Phys ph;
     int32_t row0;              // row of the link's first receiver
@@ -66,6 +69,18 @@ struct DonorLink {
     int64_t nrecv;
     int S;
     int sbp;
+};
+
+// Receivers of a link cut into chunks of rpc consecutive receivers (rpc * S
+// = 256 entries), one workgroup per (chunk, slot): the chunk's distinct donor
+// points upts[ustart[c] .. ustart[c+1]) (sorted), each entry's index among
+// them (eloc, receiver-major), and the points their gradient stencils read,
+// cpts[cstart[c] .. cstart[c+1]) (sorted; used when the state is an
+// extrapolant).  Dynamic LDS: maxu * RB + maxc * nv doubles, maxc ints.
+struct DonorBlocks {
+    const int32_t *ustart, *upts, *cstart, *cpts;
+    const int16_t *eloc;
+    int nchunk, rpc, maxu, maxc;
 };
 
 // extrapolated donor states at listed points for nj target times:
@@ -87,6 +102,9 @@ hipError_t launch_grad(const GridDev &g, int sbp, double gm1, const double *q, d
 hipError_t launch_rhs(const GridDev &g, const GridDev *g_dev, int sbp, const Phys &ph, const double *q,
                       const double *grad, double *F, const Combine &cb, hipStream_t st);
 hipError_t launch_donor(const DonorLink &a, hipStream_t st);
+// one launch: (extrapolation when a.m > 0,) values and gather per chunk
+hipError_t launch_donor_block(const DonorLink &a, const DonorBlocks &b, hipStream_t st);
+size_t donor_block_lds(int dim, int maxu, int maxc);
 hipError_t launch_extrap(const Extrap &a, hipStream_t st);
 // fused LDS-tiled 2D right-hand side (gradients, fluxes, divergence, SAT, AB update)
 struct TileShape { int tx, ty, tm; };

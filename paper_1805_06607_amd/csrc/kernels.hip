@@ -866,6 +866,137 @@ __global__ void __launch_bounds__(256) k_donor_gather(DonorLink a)
     }
 }
 
+// Receiver rows of one chunk of receivers for slot j = blockIdx.y in one
+// workgroup: (EXT) the extrapolant at the points the chunk's gradient
+// stencils read, each value with the same separately rounded products and
+// sums as k_extrap, into LDS; q and the Cartesian viscous fluxes once per
+// distinct donor point into LDS; then each receiver's S entries weighted and
+// added by the same butterfly as k_donor_gather.
+template <int DIM, int SBP, int CART, int EXT>
+__global__ void __launch_bounds__(256) k_donor_block(DonorLink a, DonorBlocks b)
+{
+    constexpr int NV = DIM + 2;
+    constexpr int RB = NV + DIM * (NV - 1);
+    constexpr int NT = 256;
+    extern __shared__ double sh[];
+    double *sV = sh;                                   // maxu x RB
+    double *sQ = sh + (size_t)b.maxu * RB;             // NV x maxc
+    int32_t *sI = reinterpret_cast<int32_t *>(sQ + (size_t)b.maxc * NV);   // maxc
+    const int ch = blockIdx.x, j = blockIdx.y, tid = threadIdx.x;
+    const double *y = nullptr;
+    double *outp = nullptr;
+    double bj[MAXH];
+#pragma unroll
+    for (int jj = 0; jj < MAXJ; ++jj)
+        if (jj == j) {
+            y = a.ys[jj];
+            outp = a.out[jj];
+#pragma unroll
+            for (int hh = 0; hh < MAXH; ++hh) bj[hh] = a.beta[jj][hh];
+        }
+    const int64_t N = a.g.npts;
+    const int u0 = b.ustart[ch], nu = b.ustart[ch + 1] - u0;
+    int c0 = 0, nc = 0;
+    if constexpr (EXT) {
+        c0 = b.cstart[ch];
+        nc = b.cstart[ch + 1] - c0;
+        const int mh = a.m;
+        // batches of XB items per thread: every load of a batch is issued
+        // before the first sum
+        constexpr int XB = 4;
+        for (int base = 0; base < nc * NV; base += NT * XB) {
+            double ly[XB], lh[XB][MAXH];
+            int64_t el[XB];
+#pragma unroll
+            for (int r = 0; r < XB; ++r) {
+                const int i = base + r * NT + tid;
+                el[r] = -1;
+                if (i < nc * NV) {
+                    const int v = i / nc, ii = i - v * nc;
+                    el[r] = (int64_t)v * N + b.cpts[c0 + ii];
+                    ly[r] = y[el[r]];
+#pragma unroll
+                    for (int hh = 0; hh < MAXH; ++hh)
+                        if (hh < mh) lh[r][hh] = a.hist[hh][el[r]];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < XB; ++r) {
+                const int i = base + r * NT + tid;
+                if (el[r] < 0) continue;
+                const int v = i / nc, ii = i - v * nc;
+                double acc = ly[r];
+#pragma unroll
+                for (int hh = 0; hh < MAXH; ++hh)
+                    if (hh < mh) acc = add_nc(acc, bj[hh], lh[r][hh]);
+                sQ[(size_t)v * b.maxc + ii] = acc;
+                if (v == 0) sI[ii] = (int32_t)(el[r] - (int64_t)v * N);
+            }
+        }
+        __syncthreads();
+    }
+    auto qload = [&](int64_t idx, double *o) {
+        if constexpr (EXT) {
+            int lo = 0, hi = nc;                       // first entry >= idx (present by construction)
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (sI[mid] < idx) lo = mid + 1; else hi = mid;
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) o[v] = sQ[(size_t)v * b.maxc + lo];
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) o[v] = y[v * N + idx];
+        }
+    };
+    for (int u = tid; u < nu; u += NT) {
+        const int64_t p = b.upts[u0 + u];
+        double qp[NV];
+        qload(p, qp);
+        int ic[3];
+        coords(a.g, p, ic);
+        double gr[DIM + 1][DIM];
+        gradient<DIM, SBP, CART>(a.g, p, ic, a.ph.gamma - 1.0, qload, gr);
+        double u_[DIM];
+        double ri = 1.0 / qp[0];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) u_[i] = qp[1 + i] * ri;
+        double Fv[DIM][DIM + 1];
+        viscous_flux<DIM>(a.ph, u_, gr, Fv);
+        double *o = sV + (size_t)u * RB;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) o[v] = qp[v];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+#pragma unroll
+            for (int v = 1; v < NV; ++v) o[NV + d * (NV - 1) + (v - 1)] = Fv[d][v - 1];
+    }
+    __syncthreads();
+    const int kk = tid / a.S, e = tid - kk * a.S;
+    const int64_t k = (int64_t)ch * b.rpc + kk;
+    const bool ok = kk < b.rpc && k < a.nrecv;
+    double val[RB];
+    if (ok) {
+        const int64_t ent = k * a.S + e;
+        const double w = a.w[ent];
+        const double *vrow = sV + (size_t)b.eloc[ent] * RB;
+#pragma unroll
+        for (int t = 0; t < RB; ++t) val[t] = w * vrow[t];
+    } else {
+#pragma unroll
+        for (int t = 0; t < RB; ++t) val[t] = 0.0;
+    }
+    for (int off = 1; off < a.S; off <<= 1) {
+#pragma unroll
+        for (int t = 0; t < RB; ++t) val[t] += __shfl_xor(val[t], off, 64);
+    }
+    if (ok && e == 0) {
+        double *o = outp + (int64_t)(a.row0 + k) * RB;
+#pragma unroll
+        for (int t = 0; t < RB; ++t) o[t] = val[t];
+    }
+}
+
 // extrapolated donor states at the donor-stencil points of mid-step links:
 // one lane per (slot, point, variable)
 __global__ void __launch_bounds__(256) k_extrap(Extrap a)
@@ -1151,6 +1282,41 @@ hipError_t launch_donor(const DonorLink &a, hipStream_t st)
         hipLaunchKernelGGL((k_donor_gather<10>), dim3(nblk(gl, 256)), dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL((k_donor_gather<17>), dim3(nblk(gl, 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+size_t donor_block_lds(int dim, int maxu, int maxc)
+{
+    int nv = dim + 2, rb = nv + dim * (nv - 1);
+    return ((size_t)maxu * rb + (size_t)maxc * nv) * 8 + (size_t)maxc * 4;
+}
+
+#define DISPATCH_BLOCK(DIM, SBP, CART)                                                                   \
+    do {                                                                                                 \
+        if (ext)                                                                                         \
+            hipLaunchKernelGGL((k_donor_block<DIM, SBP, CART, 1>), grid, dim3(256), lds, st, a, b);      \
+        else                                                                                             \
+            hipLaunchKernelGGL((k_donor_block<DIM, SBP, CART, 0>), grid, dim3(256), lds, st, a, b);      \
+    } while (0)
+
+// every receiver's S entries share one wavefront; S * rpc <= 256
+hipError_t launch_donor_block(const DonorLink &a, const DonorBlocks &b, hipStream_t st)
+{
+    if (a.nrecv == 0 || a.nj == 0) return hipSuccess;
+    if (a.S < 1 || a.S > 64 || (a.S & (a.S - 1)) || b.rpc * a.S > 256 || a.nj > MAXJ || a.m < 0 ||
+        a.m > MAXH || (int64_t)b.nchunk * b.rpc < a.nrecv)
+        return hipErrorInvalidValue;
+    const bool ext = a.m > 0;
+    const GridDev &g = a.g;
+    size_t lds = donor_block_lds(g.dim, b.maxu, ext ? b.maxc : 0);
+    dim3 grid(b.nchunk, a.nj);
+    if (g.dim == 2 && a.sbp == 21 && g.cartesian) DISPATCH_BLOCK(2, 21, 1);
+    else if (g.dim == 2 && a.sbp == 21) DISPATCH_BLOCK(2, 21, 0);
+    else if (g.dim == 2 && a.sbp == 42 && g.cartesian) DISPATCH_BLOCK(2, 42, 1);
+    else if (g.dim == 2 && a.sbp == 42) DISPATCH_BLOCK(2, 42, 0);
+    else if (g.dim == 3 && a.sbp == 21 && g.cartesian) DISPATCH_BLOCK(3, 21, 1);
+    else if (g.dim == 3 && a.sbp == 42 && g.cartesian) DISPATCH_BLOCK(3, 42, 1);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

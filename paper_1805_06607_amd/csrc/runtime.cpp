@@ -61,6 +61,13 @@ struct Link {
     std::vector<int32_t> upts;   // unique donor points of the link
     int32_t *upts_d = nullptr;
     double *vals_d = nullptr;    // r_max x nu x RB donor values
+    // chunked form for the one-launch donor kernel (mrk::DonorBlocks)
+    bool blk = false;
+    int nchunk = 0, rpc = 0, maxu = 0, maxc = 0;
+    std::vector<int32_t> bus, bup, bcs, bcp;
+    std::vector<int16_t> bel;
+    int32_t *bus_d = nullptr, *bup_d = nullptr, *bcs_d = nullptr, *bcp_d = nullptr;
+    int16_t *bel_d = nullptr;
 };
 
 // Cross-stream order inside one macrostep call.  Stream s (one per grid)
@@ -130,6 +137,7 @@ struct mr_ctx {
     int tgrid = -1, tmax = 0, tcount = 0;    // tgrid -2: every grid
     std::vector<int> tgrid_of;                // grid of each timed launch
     bool two_pass = false;    // 2D: use the two-kernel (gradient pass) right-hand side
+    bool donor_blocks = true; // one-launch donor data for links whose chunks fit one workgroup
     // macrosteps: one stream per grid, ordered by events (Order); -1: when
     // the grids hold at least kMultiStreamPoints points in all
     int multi_stream = -1;
@@ -344,6 +352,59 @@ void build_closure(const mr_ctx *c, int d, GridHost &D)
         if (mark[p]) D.closure.push_back((int32_t)p);
 }
 
+// chunks of rpc = 256 / S consecutive receivers: distinct donor points,
+// each entry's index among them, and the points their gradient stencils read
+void build_blocks(const mr_ctx *c, Link &L)
+{
+    const GridHost &D = c->G[L.dg];
+    const int S = c->S;
+    L.rpc = 256 / S;
+    L.nchunk = (int)((L.n + L.rpc - 1) / L.rpc);
+    L.bus.assign(1, 0);
+    L.bcs.assign(1, 0);
+    L.bup.clear();
+    L.bcp.clear();
+    L.bel.assign((size_t)L.n * S, 0);
+    L.maxu = L.maxc = 0;
+    std::vector<int> off;
+    for (int ch = 0; ch < L.nchunk; ++ch) {
+        int64_t r0 = (int64_t)ch * L.rpc, r1 = std::min<int64_t>(L.n, r0 + L.rpc);
+        std::vector<int32_t> U;
+        for (int64_t r = r0; r < r1; ++r)
+            for (int e = 0; e < S; ++e) U.push_back(c->ept[(size_t)(L.first + r) * S + e]);
+        std::sort(U.begin(), U.end());
+        U.erase(std::unique(U.begin(), U.end()), U.end());
+        for (int64_t r = r0; r < r1; ++r)
+            for (int e = 0; e < S; ++e) {
+                int32_t q = c->ept[(size_t)(L.first + r) * S + e];
+                L.bel[(size_t)r * S + e] = (int16_t)(std::lower_bound(U.begin(), U.end(), q) - U.begin());
+            }
+        std::vector<int32_t> C;
+        for (int32_t p : U) {
+            C.push_back(p);
+            int ic[3] = {(int)(p % D.n[0]), (int)((p / D.n[0]) % D.n[1]), (int)(p / ((int64_t)D.n[0] * D.n[1]))};
+            for (int m = 0; m < D.dim; ++m) {
+                row_offsets(c->P.sbp, D.cls[(size_t)m * D.npts + p] & 15, off);
+                for (int o : off) {
+                    int j = ic[m] + o;
+                    if (D.periodic[m]) j = ((j % D.n[m]) + D.n[m]) % D.n[m];
+                    C.push_back((int32_t)(p + (int64_t)(j - ic[m]) * D.stride[m]));
+                }
+            }
+        }
+        std::sort(C.begin(), C.end());
+        C.erase(std::unique(C.begin(), C.end()), C.end());
+        L.maxu = std::max(L.maxu, (int)U.size());
+        L.maxc = std::max(L.maxc, (int)C.size());
+        L.bup.insert(L.bup.end(), U.begin(), U.end());
+        L.bcp.insert(L.bcp.end(), C.begin(), C.end());
+        L.bus.push_back((int32_t)L.bup.size());
+        L.bcs.push_back((int32_t)L.bcp.size());
+    }
+    // one workgroup's LDS; stencils of 64 entries (3D) keep the two-launch form
+    L.blk = S <= 16 && mrk::donor_block_lds(D.dim, L.maxu, L.maxc) <= 64 * 1024;
+}
+
 struct Carver {
     char *base;
     size_t off = 0;
@@ -389,6 +450,11 @@ size_t layout(mr_ctx *c, char *base)
     for (Link &L : c->links) {
         L.upts_d = cv.take<int32_t>(L.upts.size() + 1);
         L.vals_d = cv.take<double>((size_t)c->rmax * L.upts.size() * RB + 1);
+        L.bus_d = cv.take<int32_t>(L.bus.size());
+        L.bcs_d = cv.take<int32_t>(L.bcs.size());
+        L.bup_d = cv.take<int32_t>(L.bup.size() + 1);
+        L.bcp_d = cv.take<int32_t>(L.bcp.size() + 1);
+        L.bel_d = cv.take<int16_t>(L.bel.size() + 1);
     }
     c->grids_d = cv.take<GridDev>(c->G.size());
     c->partial = cv.take<double>(1024);
@@ -484,6 +550,23 @@ std::pair<int, int> &ord_rd(mr_ctx *c, int g, int k) { return c->ord.rd[(size_t)
 
 int link_index(const mr_ctx *c, const Link &L) { return (int)(&L - c->links.data()); }
 
+bool use_blocks(const mr_ctx *c, const Link &L) { return c->donor_blocks && L.blk; }
+
+mrk::DonorBlocks link_blocks(const Link &L)
+{
+    mrk::DonorBlocks b{};
+    b.ustart = L.bus_d;
+    b.upts = L.bup_d;
+    b.cstart = L.bcs_d;
+    b.cpts = L.bcp_d;
+    b.eloc = L.bel_d;
+    b.nchunk = L.nchunk;
+    b.rpc = L.rpc;
+    b.maxu = L.maxu;
+    b.maxc = L.maxc;
+    return b;
+}
+
 // donor data from the donor grid's state y into out (one target time; k > 0
 // names the receiving grid's slice for the cross-stream order)
 int link_current(mr_ctx *c, const Link &L, const double *y, double *out, int si, int k)
@@ -496,7 +579,10 @@ int link_current(mr_ctx *c, const Link &L, const double *y, double *out, int si,
         int rc = ord_need(c, si, ord_rd(c, L.rg, k));     // rows last read by the receiver at k
         if (rc) return rc;
     }
-    HIPCHK(c, mrk::launch_donor(a, sst(c, si)));
+    if (use_blocks(c, L))
+        HIPCHK(c, mrk::launch_donor_block(a, link_blocks(L), sst(c, si)));
+    else
+        HIPCHK(c, mrk::launch_donor(a, sst(c, si)));
     if (si >= 0) {
         ord_op(c, si);
         ord_wr(c, link_index(c, L), k) = {si, c->ord.pos[si]};
@@ -527,7 +613,7 @@ int donor_future(mr_ctx *c, int d, int k, int si)
     x.np = (int64_t)D.closure.size();
     bool need[mrk::MAXJ + 1] = {};
     for (const Link &L : c->links) {
-        if (L.dg != d) continue;
+        if (L.dg != d || use_blocks(c, L)) continue;
         int per_g = c->rmax / c->G[L.rg].rate;
         for (int jp = 1; jp < per_d; ++jp)
             if (kprime(jp) % per_g == 0) need[jp] = true;
@@ -539,14 +625,21 @@ int donor_future(mr_ctx *c, int d, int k, int si)
         x.out[x.nj] = D.ext[jp - 1];
         x.nj++;
     }
-    HIPCHK(c, mrk::launch_extrap(x, st));
-    ord_op(c, si);
+    if (x.nj) {
+        HIPCHK(c, mrk::launch_extrap(x, st));
+        ord_op(c, si);
+    }
     for (const Link &L : c->links) {
         if (L.dg != d) continue;
         const GridHost &R = c->G[L.rg];
         int per_g = c->rmax / R.rate;
+        const bool blk = use_blocks(c, L);
         mrk::DonorLink a = link_base(c, L);
         a.nj = 0;
+        if (blk) {
+            a.m = x.m;
+            for (int j = 0; j < x.m; ++j) a.hist[j] = x.hist[j];
+        }
         int kps[mrk::MAXJ];
         for (int jp = 1; jp < per_d; ++jp) {
             int kp = kprime(jp);
@@ -556,12 +649,20 @@ int donor_future(mr_ctx *c, int d, int k, int si)
                 if (rc) return rc;
             }
             kps[a.nj] = kp;
-            a.ys[a.nj] = D.ext[jp - 1];
+            if (blk) {
+                a.ys[a.nj] = D.y[D.cur];
+                for (int j = 0; j < x.m; ++j) a.beta[a.nj][j] = c->beta[d][jp][j];
+            } else {
+                a.ys[a.nj] = D.ext[jp - 1];
+            }
             a.out[a.nj] = recv_slice(c, R, kp);
             a.nj++;
         }
         if (!a.nj) continue;
-        HIPCHK(c, mrk::launch_donor(a, st));
+        if (blk)
+            HIPCHK(c, mrk::launch_donor_block(a, link_blocks(L), st));
+        else
+            HIPCHK(c, mrk::launch_donor(a, st));
         if (si >= 0) {
             ord_op(c, si);
             for (int j = 0; j < a.nj; ++j) ord_wr(c, link_index(c, L), kps[j]) = {si, c->ord.pos[si]};
@@ -875,6 +976,7 @@ int mr_finalize(mr_ctx *c, size_t *bytes)
         L.upts.erase(std::unique(L.upts.begin(), L.upts.end()), L.upts.end());
         for (size_t e = e0; e < e1; ++e)
             c->euid[e] = (int32_t)(std::lower_bound(L.upts.begin(), L.upts.end(), c->ept[e]) - L.upts.begin());
+        build_blocks(c, L);
     }
     c->ws_bytes = layout(c, nullptr);
     c->finalized = true;
@@ -929,8 +1031,17 @@ int mr_bind_workspace(mr_ctx *c, void *dev, size_t bytes)
         HIPCHK(c, hipMemcpyAsync(c->euid_d, c->euid.data(), R * c->S * 4, hipMemcpyHostToDevice, c->st));
         HIPCHK(c, hipMemcpyAsync(c->ew_d, c->ew.data(), R * c->S * 8, hipMemcpyHostToDevice, c->st));
     }
-    for (Link &L : c->links)
+    for (Link &L : c->links) {
         HIPCHK(c, hipMemcpyAsync(L.upts_d, L.upts.data(), L.upts.size() * 4, hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, hipMemcpyAsync(L.bus_d, L.bus.data(), L.bus.size() * 4, hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, hipMemcpyAsync(L.bcs_d, L.bcs.data(), L.bcs.size() * 4, hipMemcpyHostToDevice, c->st));
+        if (!L.bup.empty())
+            HIPCHK(c, hipMemcpyAsync(L.bup_d, L.bup.data(), L.bup.size() * 4, hipMemcpyHostToDevice, c->st));
+        if (!L.bcp.empty())
+            HIPCHK(c, hipMemcpyAsync(L.bcp_d, L.bcp.data(), L.bcp.size() * 4, hipMemcpyHostToDevice, c->st));
+        if (!L.bel.empty())
+            HIPCHK(c, hipMemcpyAsync(L.bel_d, L.bel.data(), L.bel.size() * 2, hipMemcpyHostToDevice, c->st));
+    }
     HIPCHK(c, hipMemcpyAsync(c->grids_d, devs.data(), devs.size() * sizeof(GridDev), hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
     c->bound = true;
@@ -1193,6 +1304,9 @@ int mr_set_option(mr_ctx *c, const char *name, int64_t value)
     } else if (!strcmp(name, "multi_stream")) {
         if (value != 0 && value != 1) return fail(c, MR_ERR_ARG, "multi_stream must be 0 or 1");
         c->multi_stream = (int)value;
+    } else if (!strcmp(name, "donor_blocks")) {
+        if (value != 0 && value != 1) return fail(c, MR_ERR_ARG, "donor_blocks must be 0 or 1");
+        c->donor_blocks = value != 0;
     } else if (!strcmp(name, "graph")) {
         if (value != 0 && value != 1) return fail(c, MR_ERR_ARG, "graph must be 0 or 1");
         if (value) return fail(c, MR_ERR_UNSUPPORTED, "graph replay of macrosteps is switched off");

@@ -30,6 +30,11 @@ CASES = {
 }
 
 
+# donor data: one launch per link and donor step (chunked receivers, the
+# default for 2D stencils) or values at distinct donor points, then a gather
+DONOR_MODES = {"blocks": {}, "two_phase": {"donor_blocks": 0}}
+
+
 @pytest.fixture(scope="module")
 def torch():
     return require_gpu()
@@ -62,14 +67,17 @@ def test_rhs_parity(torch, case, two_pass):
         assert np.all(_np(got[g])[:, ~act] == 0.0)
 
 
+@pytest.mark.parametrize("mode", list(DONOR_MODES))
 @pytest.mark.parametrize("case", ["vortex_box", "cylinder_small"])
-def test_receiver_data_parity(torch, case):
+def test_receiver_data_parity(torch, case, mode):
     from oracle import OracleSystem
     from paper_1805_06607_amd.system import System
     wl = CASES[case]()
     states = workloads.random_state_like(wl, seed=3, amp=0.02)
     orc = OracleSystem(wl)
     sysg = System(wl)
+    for name, value in DONOR_MODES[mode].items():
+        sysg.set_option(name, value)
     for g in range(len(wl.grids)):
         want = orc.receiver_data(g, states)
         got = _np(sysg.receiver_data(g, states))
@@ -109,11 +117,12 @@ def _run_both(wl, nmacro, options=None):
     return orc, mr, sysg
 
 
+@pytest.mark.parametrize("mode", list(DONOR_MODES))
 @pytest.mark.parametrize("case", ["vortex_box", "cylinder_small"])
-def test_mrab_parity_100_macrosteps(torch, case):
+def test_mrab_parity_100_macrosteps(torch, case, mode):
     wl = CASES[case]()
-    _say("mrab parity", case)
-    orc, mr, sysg = _run_both(wl, 100)
+    _say("mrab parity", case, mode)
+    orc, mr, sysg = _run_both(wl, 100, DONOR_MODES[mode])
     t, k = sysg.time()
     assert k == 100 and abs(t - mr.t) <= 1e-12 * mr.t
     for g in range(len(wl.grids)):
