@@ -84,6 +84,53 @@ def run_tgv3d(args):
     print(json.dumps(line), flush=True)
 
 
+def run_stability(args):
+    """Stability mode: largest stable macrostep of single- and multi-rate AB
+    (perturbation growth over 500 macrosteps from a steady state, GPU) on a
+    cylinder-like stand-in without the wall (40^2 background, 96 x 24 O-mesh,
+    uniform Mach 0.2 flow, a steady state of the discretisation), for AB3
+    and AB34 and step ratios 1..8: r_SRAB = H_max(SR) / H_max(1) as in the
+    paper's stability tables.  Prints one JSON line."""
+    import workloads
+    from paper_1805_06607_amd.system import System
+    from paper_1805_06607_amd.stability import largest_stable_by_growth
+
+    def wl_for(sr, order, m):
+        return workloads.cylinder(nbg=40, ntheta=96, nr=24, half=6.0, rate_fast=sr, order=order, hist_len=m,
+                                  wall=False, perturb=0.0)
+
+    # fastest grid's own step estimate (eq. ts_overall with CFL 1, every grid at rate 1)
+    w1 = wl_for(1, 3, 3)
+    w1.params["cfl"] = 1.0
+    s = System(w1)
+    _, dt_fast = s.timestep()
+    s.close()
+    table = {}
+    t0 = time.perf_counter()
+    for order, m in ((3, 3), (3, 4)):
+        name = f"AB{order}{m if m != order else ''}"
+        rows = []
+        for sr in (1, 2, 3, 4, 5, 6, 8):
+            g = dt_fast * sr
+            H = largest_stable_by_growth(lambda: System(wl_for(sr, order, m)), 0.1 * g, 4.0 * g, 0.005 * g)
+            rows.append({"SR": sr, "H_max": H})
+            log(f"{name} SR={sr} H_max={H:.6g}")
+        for r in rows:
+            r["r_SRAB"] = r["H_max"] / rows[0]["H_max"]
+            r["efficiency"] = r["r_SRAB"] / r["SR"]
+        table[name] = rows
+    line = {"metric": "largest stable macrostep vs step ratio (MRAB stability), 1 GPU", "unit": "non-dimensional time",
+            "value": table["AB34"][0]["H_max"], "higher_is_better": True, "n_gpus": 1, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "cylinder-like stand-in without wall: 40^2 background on [-6,6]^2 (hole r<2) + "
+                                   "96x24 O-mesh (r 0.5..3), uniform flow M 0.2, Re 200, SBP 4-2, cubic donors",
+                       "criterion": "growth of a 1e-8 random perturbation of the steady state over 500 "
+                                    "macrosteps below 100 (eigenvalue modulus above ~1.009 flagged)",
+                       "dt_fast_estimate": dt_fast},
+            "table": table, "seconds": time.perf_counter() - t0}
+    print(json.dumps(line), flush=True)
+
+
 def kernel_names(sysg, wl):
     """Kernel instantiation of each grid's fused 2D right-hand side."""
     names = []
@@ -338,7 +385,7 @@ def main():
     ap.add_argument("--ee-macrosteps", type=int, default=200)
     ap.add_argument("--ee-spinup", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--workload", default="cylinder", choices=["cylinder", "tgv3d"])
+    ap.add_argument("--workload", default="cylinder", choices=["cylinder", "tgv3d", "stability"])
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -357,6 +404,9 @@ def main():
         del a, c
     if args.workload == "tgv3d":
         run_tgv3d(args)
+        return
+    if args.workload == "stability":
+        run_stability(args)
         return
     res, wl, n_act = run_gpu(args)
     K = args.steps

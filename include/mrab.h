@@ -128,7 +128,9 @@ int mr_finalize(mr_ctx *ctx, size_t *workspace_bytes);
  * upload the tables, compute metric terms on the device. */
 int mr_bind_workspace(mr_ctx *ctx, void *dev_ptr, size_t bytes);
 
-/* Copy a grid state (device, nv x npts) into / out of the context (async). */
+/* Copy a grid state (device, nv x npts) into / out of the context (async).
+ * After mr_set_state (or mr_set_history) macrosteps need mr_mrab_start or
+ * mr_mrab_resume first (MR_ERR_STATE otherwise). */
 int mr_set_state(mr_ctx *ctx, int grid, const double *dev_q);
 int mr_get_state(mr_ctx *ctx, int grid, double *dev_q_out);
 
@@ -150,6 +152,11 @@ int mr_num_receivers(const mr_ctx *ctx, int grid, int64_t *n);
  * h = H / r_max.  Fixes H for the run. */
 int mr_timestep(mr_ctx *ctx, double *h, double *H);
 
+/* Set the macrostep H directly (h = H / r_max), instead of mr_timestep's
+ * estimate; later macrosteps need mr_mrab_start or mr_mrab_resume first.
+ * Errors: MR_ERR_SETUP (H not positive and finite). */
+int mr_set_macrostep(mr_ctx *ctx, double H);
+
 /* Bootstrap (section "Adams-Bashforth Integration"): single-rate RK at
  * h = H / r_max (Heun RK3 for order <= 3, classic RK4 for order 4) for
  * (m-1)*r_max steps from the current states at time t0, keeping F(y_n) at each
@@ -165,6 +172,21 @@ int mr_mrab_macrostep(mr_ctx *ctx, int nsteps);
  * grid g, the values the AB combination of eq. ab_general weights) into
  * dev_out (nv x npts, async).  For checkpoints and tests. */
 int mr_get_history(mr_ctx *ctx, int grid, int j, double *dev_out);
+
+/* Set history value j of grid g from dev_in (nv x npts, async), the inverse
+ * of mr_get_history.  Together with mr_set_state and mr_mrab_resume this sets
+ * the whole integrator state (each grid's state and its m right-hand-side
+ * values), e.g. to form step matrices by finite differences (section
+ * "Procedure for Determining Discrete Stability") or to restart from a
+ * checkpoint.  Errors: MR_ERR_STATE before mr_mrab_start. */
+int mr_set_history(mr_ctx *ctx, int grid, int j, const double *dev_in);
+
+/* Continue MRAB from the current states and histories at time t (async):
+ * stages every grid's next own step (eq. ab_general) and the donor data of
+ * the next macrostep's mid-step times, as the end of mr_mrab_start does;
+ * the macrostep count restarts at 0.  Errors: MR_ERR_STATE before
+ * mr_mrab_start. */
+int mr_mrab_resume(mr_ctx *ctx, double t);
 
 /* Current time and completed macrosteps. */
 int mr_time(const mr_ctx *ctx, double *t, int64_t *macrosteps);

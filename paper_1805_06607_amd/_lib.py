@@ -55,6 +55,9 @@ SIGNATURES = {
     "mr_mrab_start": [c_void_p, c_double],
     "mr_mrab_macrostep": [c_void_p, c_int],
     "mr_get_history": [c_void_p, c_int, c_int, c_void_p],
+    "mr_set_history": [c_void_p, c_int, c_int, c_void_p],
+    "mr_set_macrostep": [c_void_p, c_double],
+    "mr_mrab_resume": [c_void_p, c_double],
     "mr_time": [c_void_p, POINTER(c_double), POINTER(c_int64)],
     "mr_ab_coeffs": [c_int, c_int, c_double, POINTER(c_double)],
     "mr_kernel_timing": [c_void_p, c_int, c_int],

@@ -117,6 +117,7 @@ struct mr_ctx {
     std::vector<int32_t> ept;
     std::vector<double> ew;
     bool finalized = false, bound = false, have_dt = false, started = false;
+    bool stale = false;       // a state or history was set since the last start/resume
     size_t ws_bytes = 0;
     char *ws = nullptr;
     int rmax = 1;
@@ -824,6 +825,52 @@ int run_macrosteps(mr_ctx *c, int nsteps, bool ms, hipStream_t origin, const EvS
     return MR_OK;
 }
 
+// from the current states and histories: stage every grid's first own step
+// and, as if every grid had just evaluated, the donor data of the next
+// macrostep's mid-step times
+int restage(mr_ctx *c)
+{
+    int m = c->P.hist_len;
+    for (size_t g = 0; g < c->G.size(); ++g) {
+        GridHost &Gh = c->G[g];
+        mrk::Combine cb{};
+        cb.m = m;
+        for (int j = 0; j < m; ++j) {
+            cb.c[j] = c->c_own[g][j];
+            cb.hist[j] = slot(c, Gh, j);
+        }
+        cb.y_next = Gh.y[1 - Gh.cur];
+        HIPCHK(c, mrk::launch_combine(nelem(Gh), Gh.y[Gh.cur], cb, c->st));
+    }
+    for (int g = 0; g < (int)c->G.size(); ++g) {
+        int rc = donor_future(c, g, c->rmax, -1);
+        if (rc) return rc;
+    }
+    return MR_OK;
+}
+
+// macrostep H: the fastest grid's step h = H / r_max and every grid's own
+// and mid-step AB coefficient rows scaled by its step H / r_g
+int set_macrostep(mr_ctx *c, double Hm)
+{
+    if (!(Hm > 0) || !std::isfinite(Hm)) return fail(c, MR_ERR_SETUP, "invalid timestep %g", Hm);
+    c->H = Hm;
+    c->h = Hm / c->rmax;
+    c->have_dt = true;
+    int m = c->P.hist_len;
+    c->c_own.assign(c->G.size(), std::vector<double>(m));
+    c->beta.assign(c->G.size(), {});
+    for (size_t g = 0; g < c->G.size(); ++g) {
+        double Hg = Hm / c->G[g].rate;
+        for (int j = 0; j < m; ++j) c->c_own[g][j] = (double)c->alpha_own[g][j] * Hg;
+        int per = c->rmax / c->G[g].rate;
+        c->beta[g].assign(per, std::vector<double>(m, 0.0));
+        for (int jp = 1; jp < per; ++jp)
+            for (int j = 0; j < m; ++j) c->beta[g][jp][j] = (double)c->alpha_mid[g][jp][j] * Hg;
+    }
+    return MR_OK;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -1054,7 +1101,7 @@ int mr_set_state(mr_ctx *c, int g, const double *q)
     if (!c->bound) return fail(c, MR_ERR_STATE, "mr_set_state before mr_bind_workspace");
     GridHost &G = c->G[g];
     HIPCHK(c, hipMemcpyAsync(G.y[G.cur], q, nelem(G) * 8, hipMemcpyDeviceToDevice, c->st));
-    c->started = false;
+    c->stale = true;
     return MR_OK;
 }
 
@@ -1117,21 +1164,8 @@ int mr_timestep(mr_ctx *c, double *h, double *H)
         }
         Hm *= c->P.cfl;
     }
-    if (!(Hm > 0) || !std::isfinite(Hm)) return fail(c, MR_ERR_SETUP, "invalid timestep %g", Hm);
-    c->H = Hm;
-    c->h = Hm / c->rmax;
-    c->have_dt = true;
-    int m = c->P.hist_len;
-    c->c_own.assign(c->G.size(), std::vector<double>(m));
-    c->beta.assign(c->G.size(), {});
-    for (size_t g = 0; g < c->G.size(); ++g) {
-        double Hg = Hm / c->G[g].rate;
-        for (int j = 0; j < m; ++j) c->c_own[g][j] = (double)c->alpha_own[g][j] * Hg;
-        int per = c->rmax / c->G[g].rate;
-        c->beta[g].assign(per, std::vector<double>(m, 0.0));
-        for (int jp = 1; jp < per; ++jp)
-            for (int j = 0; j < m; ++j) c->beta[g][jp][j] = (double)c->alpha_mid[g][jp][j] * Hg;
-    }
+    int rc = set_macrostep(c, Hm);
+    if (rc) return rc;
     if (h) *h = c->h;
     if (H) *H = c->H;
     return MR_OK;
@@ -1192,27 +1226,12 @@ int mr_mrab_start(mr_ctx *c, double t0)
                                                  g.y[g.cur], c->st));
         }
     }
-    // stage every grid's first own step
-    for (size_t g = 0; g < c->G.size(); ++g) {
-        GridHost &Gh = c->G[g];
-        mrk::Combine cb{};
-        cb.m = m;
-        for (int j = 0; j < m; ++j) {
-            cb.c[j] = c->c_own[g][j];
-            cb.hist[j] = slot(c, Gh, j);
-        }
-        cb.y_next = Gh.y[1 - Gh.cur];
-        HIPCHK(c, mrk::launch_combine(nelem(Gh), Gh.y[Gh.cur], cb, c->st));
-    }
-    // every grid has just evaluated: donor data of the first macrostep's
-    // mid-step times
-    for (int g = 0; g < (int)c->G.size(); ++g) {
-        int rc = donor_future(c, g, c->rmax, -1);
-        if (rc) return rc;
-    }
+    int rc = restage(c);
+    if (rc) return rc;
     c->t = t0 + nsteps * d;
     c->nmacro = 0;
     c->started = true;
+    c->stale = false;
     return MR_OK;
 }
 
@@ -1220,6 +1239,7 @@ int mr_mrab_macrostep(mr_ctx *c, int nsteps)
 {
     if (!c || nsteps < 0) return MR_ERR_ARG;
     if (!c->started) return fail(c, MR_ERR_STATE, "mr_mrab_macrostep before mr_mrab_start");
+    if (c->stale) return fail(c, MR_ERR_STATE, "state or history set: call mr_mrab_resume or mr_mrab_start first");
     if (nsteps == 0) return MR_OK;
     int64_t npts = 0;
     for (auto &g : c->G) npts += g.npts;
@@ -1229,6 +1249,38 @@ int mr_mrab_macrostep(mr_ctx *c, int nsteps)
         if (rc) return rc;
     }
     return run_macrosteps(c, nsteps, ms, c->st, c->eager);
+}
+
+int mr_set_macrostep(mr_ctx *c, double H)
+{
+    if (!c) return MR_ERR_ARG;
+    if (!c->finalized) return fail(c, MR_ERR_STATE, "mr_set_macrostep before mr_finalize");
+    int rc = set_macrostep(c, H);
+    if (rc) return rc;
+    c->stale = true;          // the staged own steps used the old coefficients
+    return MR_OK;
+}
+
+int mr_set_history(mr_ctx *c, int g, int j, const double *in)
+{
+    if (!c || !in || g < 0 || g >= (int)c->G.size() || j < 0 || j >= c->P.hist_len) return MR_ERR_ARG;
+    if (!c->started) return fail(c, MR_ERR_STATE, "mr_set_history before mr_mrab_start");
+    GridHost &G = c->G[g];
+    HIPCHK(c, hipMemcpyAsync(slot(c, G, j), in, nelem(G) * 8, hipMemcpyDeviceToDevice, c->st));
+    c->stale = true;
+    return MR_OK;
+}
+
+int mr_mrab_resume(mr_ctx *c, double t)
+{
+    if (!c) return MR_ERR_ARG;
+    if (!c->started) return fail(c, MR_ERR_STATE, "mr_mrab_resume before mr_mrab_start");
+    int rc = restage(c);
+    if (rc) return rc;
+    c->t = t;
+    c->nmacro = 0;
+    c->stale = false;
+    return MR_OK;
 }
 
 int mr_get_history(mr_ctx *c, int g, int j, double *out)

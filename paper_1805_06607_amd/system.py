@@ -167,11 +167,26 @@ class System:
         self._check(self.lib.mr_timestep(self.ctx, byref(h), byref(H)), "mr_timestep")
         return h.value, H.value
 
+    def set_macrostep(self, H: float):
+        """Fix the macrostep H (h = H / r_max) instead of the estimate."""
+        self._check(self.lib.mr_set_macrostep(self.ctx, H), "mr_set_macrostep")
+
     def start(self, t0: float = 0.0):
         self._check(self.lib.mr_mrab_start(self.ctx, t0), "mr_mrab_start")
 
     def macrostep(self, n: int = 1):
         self._check(self.lib.mr_mrab_macrostep(self.ctx, n), "mr_mrab_macrostep")
+
+    def set_history(self, g: int, j: int, F) -> None:
+        """History value j (0 oldest .. m-1 newest) of grid g."""
+        t = self._dev(F).reshape(self.nv, -1)
+        self._hist_keep = getattr(self, "_hist_keep", {})
+        self._hist_keep[(g, j)] = t
+        self._check(self.lib.mr_set_history(self.ctx, g, j, c_void_p(t.data_ptr())), "mr_set_history")
+
+    def resume(self, t: float = 0.0):
+        """Continue MRAB from the current states and histories at time t."""
+        self._check(self.lib.mr_mrab_resume(self.ctx, t), "mr_mrab_resume")
 
     def history(self, g: int, j: int) -> torch.Tensor:
         out = torch.empty((self.nv, self.npts(g)), dtype=torch.float64, device=self.device)

@@ -206,26 +206,30 @@ def omesh_grid(ntheta: int, nr: int, rate: int, priority: int, wall: bool = True
 
 def cylinder(nbg: int = 512, ntheta: int = 256, nr: int = 128, half: float = 20.0,
              seed: int = 1, rate_fast: int = 4, order: int = 4, hist_len: Optional[int] = None,
-             mach: float = 0.2, Re: float = 200.0, hole_r: float = 2.0) -> Workload:
+             mach: float = 0.2, Re: float = 200.0, hole_r: float = 2.0, wall: bool = True,
+             perturb: float = 1e-3) -> Workload:
     """Cylinder-like overset case: Cartesian background on [-half, half]^2
     (far-field faces) with a hole r < hole_r, and a 2D annular O-mesh
     (periodic in theta, geometric stretching 1.03 from r=0.5 to r=3) carrying an
     isothermal no-slip wall at r = 0.5.  Uniform flow at Mach 0.2 plus a seeded
-    U(-1e-3, 1e-3) perturbation of u on every background point.
+    U(-perturb, perturb) perturbation of u on every background point.  With
+    wall=False the inner face is far field too, and with perturb=0 the uniform
+    flow is then a steady state of the discretisation (a base state for step
+    matrices).
     """
     gamma = 1.4
     h = 2.0 * half / (nbg - 1)
     g0 = Grid("background", (nbg, nbg), (False, False), CARTESIAN,
               [BC_FARFIELD] * 4, 1, 0, origin=(-half, -half, 0.0), spacing=(h, h, h))
     g0.holes.append(("disk", (0.0, 0.0), hole_r))
-    g1 = omesh_grid(ntheta, nr, rate_fast, 1)
+    g1 = omesh_grid(ntheta, nr, rate_fast, 1, wall=wall)
     p_inf = 1.0 / (gamma * mach * mach)
     params = default_params(gamma=gamma, Re=Re, Pr=0.72, sbp=42, order=order,
                             hist_len=hist_len or order, interp_width=4, cfl=0.25)
     params["q_inf"] = [1.0, 1.0, 0.0, p_inf / (gamma - 1.0) + 0.5, 0.0]
     params["T_wall"] = p_inf / 1.0
     rng = np.random.Generator(np.random.PCG64(seed))
-    du = rng.uniform(-1e-3, 1e-3, size=g0.npts)
+    du = rng.uniform(-perturb, perturb, size=g0.npts) if perturb > 0 else np.zeros(g0.npts)
     q0 = []
     for g, pert in ((g0, du), (g1, 0.0)):
         one = np.ones(g.npts)
