@@ -131,6 +131,59 @@ def run_stability(args):
     print(json.dumps(line), flush=True)
 
 
+def run_batch(args):
+    """Batch mode: 64 independent vortex systems of uneven size (background
+    side U{64..512} at spacing 10/64, patch side U{S/4..S/2} at half spacing,
+    seeded vortex positions, patch rate from {1, 2, 4}; SBP 2-1, bilinear,
+    AB3), advanced together (one work-list launch per kind of job and
+    micro-time) and, for comparison, one after another on their own.
+    Prints one JSON line."""
+    import torch
+    import workloads
+    from paper_1805_06607_amd.batch import Batch
+    from paper_1805_06607_amd.system import System
+    wls = workloads.batch_vortex(64, seed=3)
+    log("setup 64 systems")
+    systems = []
+    for wl in wls:
+        s = System(wl)
+        s.timestep()
+        s.start(0.0)
+        systems.append(s)
+    pts = sum(g.rate * int(ib.sum()) for s in systems for g, ib in zip(s.wl.grids, s.iblanks))
+    npts = sum(g.npts for wl in wls for g in wl.grids)
+    b = Batch(systems)
+    b.macrostep(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.macrostep(args.steps)
+    torch.cuda.synchronize()
+    el_b = time.perf_counter() - t0
+    for s in systems:
+        s.macrostep(args.warmup)
+    torch.cuda.synchronize()
+    ks = max(1, args.steps // 5)
+    t0 = time.perf_counter()
+    for _ in range(ks):
+        for s in systems:
+            s.macrostep(1)
+    torch.cuda.synchronize()
+    el_s = time.perf_counter() - t0
+    bpp = 8 * 4 * (3 + 2)
+    line = {"metric": "batched MRAB pt-updates/s (64 uneven systems), 1 GPU", "value": pts * args.steps / el_b,
+            "unit": "pt-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": el_b / args.steps * 1e3, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "64 vortex systems, background U{64..512}^2 + patch U{S/4..S/2}^2, rates "
+                                   "{1,2,4}, SBP 2-1, bilinear, AB3, seed 3", "points": npts,
+                       "point_updates_per_macrostep": pts},
+            "one_system_at_a_time": {"value": pts * ks / el_s, "ms_per_step": el_s / ks * 1e3},
+            "batch_speedup": (el_s / ks) / (el_b / args.steps),
+            "algorithmic_GB_per_s": pts * bpp * args.steps / el_b / 1e9,
+            "bytes_per_point": bpp}
+    b.close()
+    print(json.dumps(line), flush=True)
+
+
 def kernel_names(sysg, wl):
     """Kernel instantiation of each grid's fused 2D right-hand side."""
     names = []
@@ -385,7 +438,7 @@ def main():
     ap.add_argument("--ee-macrosteps", type=int, default=200)
     ap.add_argument("--ee-spinup", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--workload", default="cylinder", choices=["cylinder", "tgv3d", "stability"])
+    ap.add_argument("--workload", default="cylinder", choices=["cylinder", "tgv3d", "stability", "batch"])
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -407,6 +460,9 @@ def main():
         return
     if args.workload == "stability":
         run_stability(args)
+        return
+    if args.workload == "batch":
+        run_batch(args)
         return
     res, wl, n_act = run_gpu(args)
     K = args.steps

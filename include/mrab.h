@@ -256,6 +256,31 @@ int mr_autotune(mr_ctx *ctx, int reps);
  * a NaN or Inf, and the largest |q| in *maxabs. */
 int mr_guard(mr_ctx *ctx, double *maxabs);
 
+/* Batches (many independent systems advanced together).  A batch holds
+ * finalized 2D contexts sharing one stream and one SBP operator, whose links
+ * all take the one-launch donor form; their macrosteps H and step ratios may
+ * differ (every system's largest rate must divide the batch's least common
+ * multiple R <= 64).  One batch macrostep advances every system by one of its
+ * own macrosteps: for each of the R micro-times, one work-list launch per
+ * kind of job -- donor data at the current time, fused right-hand sides (one
+ * launch per tile shape and grid kind), mid-step donor data -- over all
+ * systems that step then.  The launches run the same per-tile and per-chunk
+ * code as each system's own mr_mrab_macrostep, so every system's result is
+ * the same.  The launch plan (jobs in device memory, built on the host from
+ * the systems' bookkeeping, one plan period of macrosteps) is rebuilt when a
+ * system was stepped on its own, restarted, or changed its step, tile shapes
+ * or options.  The library allocates nothing: mr_batch_workspace_size
+ * reports the bytes the caller binds.  Errors: MR_ERR_ARG, MR_ERR_STATE (a
+ * context not finalized; a system not started), MR_ERR_UNSUPPORTED (3D, the
+ * gradient-pass form, two-launch donor links, mixed operators or streams). */
+typedef struct mr_batch mr_batch;
+int mr_batch_create(mr_ctx *const *ctxs, int n, mr_batch **out);
+int mr_batch_workspace_size(const mr_batch *batch, size_t *bytes);
+int mr_batch_bind_workspace(mr_batch *batch, void *dev_ptr, size_t bytes);
+int mr_batch_macrostep(mr_batch *batch, int nsteps);
+const char *mr_batch_last_error(const mr_batch *batch);
+void mr_batch_destroy(mr_batch *batch);
+
 const char *mr_last_error(const mr_ctx *ctx);
 void mr_destroy(mr_ctx *ctx);
 

@@ -68,6 +68,12 @@ SIGNATURES = {
     "mr_get_tile_shape": [c_void_p, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_int)],
     "mr_autotune": [c_void_p, c_int],
     "mr_guard": [c_void_p, POINTER(c_double)],
+    "mr_batch_create": [POINTER(c_void_p), c_int, POINTER(c_void_p)],
+    "mr_batch_workspace_size": [c_void_p, POINTER(c_size_t)],
+    "mr_batch_bind_workspace": [c_void_p, c_void_p, c_size_t],
+    "mr_batch_macrostep": [c_void_p, c_int],
+    "mr_batch_last_error": [c_void_p],
+    "mr_batch_destroy": [c_void_p],
     "mr_last_error": [c_void_p],
     "mr_destroy": [c_void_p],
 }
@@ -87,6 +93,8 @@ def load():
             f.restype = c_int
         lib.mr_last_error.restype = c_char_p
         lib.mr_destroy.restype = None
+        lib.mr_batch_last_error.restype = c_char_p
+        lib.mr_batch_destroy.restype = None
         _lib = lib
     return _lib
 

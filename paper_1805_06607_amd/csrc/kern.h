@@ -83,6 +83,14 @@ struct DonorBlocks {
     int nchunk, rpc, maxu, maxc;
 };
 
+// one link's donor data in a work-list launch (chunks chunk0 .. chunk0 +
+// b.nchunk - 1 of the concatenated list)
+struct LinkJob {
+    DonorLink a;
+    DonorBlocks b;
+    int chunk0;
+};
+
 // extrapolated donor states at listed points for nj target times:
 // out[j][v*N + p] = y[v*N + p] + sum_h beta[j][h] hist[h][v*N + p]
 struct Extrap {
@@ -108,6 +116,23 @@ size_t donor_block_lds(int dim, int maxu, int maxc);
 hipError_t launch_extrap(const Extrap &a, hipStream_t st);
 // fused LDS-tiled 2D right-hand side (gradients, fluxes, divergence, SAT, AB update)
 struct TileShape { int tx, ty, tm; };
+// one grid evaluation in a work-list launch: tiles tile0 .. tile0 + ntx*nty - 1
+// of the concatenated list (g.recv: the receiver rows of this evaluation)
+struct TileJob {
+    GridDev g;
+    const double *q;
+    double *F;
+    Combine cb;
+    int ntx, nty, tile0;
+};
+// jobs (device, ordered by tile0, all of one kind: sbp, cart, shape), nblk
+// tiles in all
+hipError_t launch_rhs_tiles(const TileJob *jobs, int njobs, int nblk, int sbp, int cart, int shape, const Phys &ph,
+                            hipStream_t st);
+// jobs (device, ordered by chunk0, one kind: dim, sbp, cart, ext), nchunk
+// chunks in all, up to maxnj slots, lds bytes per workgroup
+hipError_t launch_donor_blocks(const LinkJob *jobs, int njobs, int nchunk, int maxnj, int dim, int sbp, int cart,
+                               bool ext, size_t lds, hipStream_t st);
 constexpr int NUM_TILE_SHAPES = 8;
 extern const TileShape kTileShapes[NUM_TILE_SHAPES];
 int default_tile_shape(const GridDev &g);

@@ -477,9 +477,18 @@ __device__ __forceinline__ int wrap1(int i, int n)
     return i;
 }
 
+// XCD-aware order: consecutive workgroups go to different XCDs, so give each
+// XCD a contiguous range of tiles (neighbours share halos in its L2); a
+// bijection when the tile count is a multiple of 8, identity otherwise
+__device__ __forceinline__ int xcd_tile(int b, int nblk)
+{
+    return (nblk % 8) ? b : (b % 8) * (nblk / 8) + b / 8;
+}
+
+// the work of one workgroup: the tile with corner (x0, y0) of grid g
 template <int SBP, int CART, int TX_, int TY_, int TM_>
-__global__ void __launch_bounds__(TX_ * TY_ * TM_, 2)
-k_rhs_tile2d(GridDev g, Phys ph, const double *__restrict__ q, double *__restrict__ F, Combine cb, int ntx, int nty)
+__device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph, const double *__restrict__ q,
+                                                double *__restrict__ F, const Combine &cb, int x0, int y0)
 {
     using C = TileCfg<SBP, TX_, TY_, TM_>;
     constexpr int NT = C::NT;
@@ -490,13 +499,6 @@ k_rhs_tile2d(GridDev g, Phys ph, const double *__restrict__ q, double *__restric
     __shared__ double sM[CART ? 1 : 5][CART ? 1 : MN];   // M00 M01 M10 M11 J on the flux region
     __shared__ int8_t sC[2][PY][PX];                 // class bytes
 
-    // XCD-aware order: consecutive workgroups go to different XCDs, so give
-    // each XCD a contiguous range of tiles (neighbours share halos in its L2);
-    // a bijection when the tile count is a multiple of 8, identity otherwise
-    const int nblk = ntx * nty;
-    const int b = blockIdx.x;
-    const int tile = (nblk % 8) ? b : (b % 8) * (nblk / 8) + b / 8;
-    const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
     const int nx = g.n[0], ny = g.n[1];
     const int64_t N = g.npts;
     const double gm1 = ph.gamma - 1.0;
@@ -790,6 +792,33 @@ k_rhs_tile2d(GridDev g, Phys ph, const double *__restrict__ q, double *__restric
     }
 }
 
+// one grid: tile blockIdx.x (XCD-ordered) of an ntx x nty tiling
+template <int SBP, int CART, int TX_, int TY_, int TM_>
+__global__ void __launch_bounds__(TX_ * TY_ * TM_, 2)
+k_rhs_tile2d(GridDev g, Phys ph, const double *__restrict__ q, double *__restrict__ F, Combine cb, int ntx, int nty)
+{
+    const int tile = xcd_tile(blockIdx.x, ntx * nty);
+    rhs_tile2d_body<SBP, CART, TX_, TY_, TM_>(g, ph, q, F, cb, (tile % ntx) * TX_, (tile / ntx) * TY_);
+}
+
+// a work list of grid evaluations (TileJob, ordered by first tile): the
+// workgroup's tile in the concatenated tilings (XCD-ordered over the whole
+// list), its job found by bisection on the first-tile offsets
+template <int SBP, int CART, int TX_, int TY_, int TM_>
+__global__ void __launch_bounds__(TX_ * TY_ * TM_, 2)
+k_rhs_tiles(const TileJob *__restrict__ jobs, int njobs, int nblk, Phys ph)
+{
+    const int b = xcd_tile(blockIdx.x, nblk);
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile0 <= b) lo = mid; else hi = mid - 1;
+    }
+    const TileJob &J = jobs[lo];
+    const int tile = b - J.tile0;
+    rhs_tile2d_body<SBP, CART, TX_, TY_, TM_>(J.g, ph, J.q, J.F, J.cb, (tile % J.ntx) * TX_, (tile / J.ntx) * TY_);
+}
+
 // ---------------------------------------------------------------- donors
 // Donor values: q and the Cartesian viscous flux vectors at each unique donor
 // point, from the donor grid's state and its own SBP gradient.
@@ -873,16 +902,15 @@ __global__ void __launch_bounds__(256) k_donor_gather(DonorLink a)
 // distinct donor point into LDS; then each receiver's S entries weighted and
 // added by the same butterfly as k_donor_gather.
 template <int DIM, int SBP, int CART, int EXT>
-__global__ void __launch_bounds__(256) k_donor_block(DonorLink a, DonorBlocks b)
+__device__ __forceinline__ void donor_block_body(const DonorLink &a, const DonorBlocks &b, int ch, int j, double *sh)
 {
     constexpr int NV = DIM + 2;
     constexpr int RB = NV + DIM * (NV - 1);
     constexpr int NT = 256;
-    extern __shared__ double sh[];
     double *sV = sh;                                   // maxu x RB
     double *sQ = sh + (size_t)b.maxu * RB;             // NV x maxc
     int32_t *sI = reinterpret_cast<int32_t *>(sQ + (size_t)b.maxc * NV);   // maxc
-    const int ch = blockIdx.x, j = blockIdx.y, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const double *y = nullptr;
     double *outp = nullptr;
     double bj[MAXH];
@@ -995,6 +1023,32 @@ __global__ void __launch_bounds__(256) k_donor_block(DonorLink a, DonorBlocks b)
 #pragma unroll
         for (int t = 0; t < RB; ++t) o[t] = val[t];
     }
+}
+
+// one link: chunk blockIdx.x, slot blockIdx.y
+template <int DIM, int SBP, int CART, int EXT>
+__global__ void __launch_bounds__(256) k_donor_block(DonorLink a, DonorBlocks b)
+{
+    extern __shared__ double sh[];
+    donor_block_body<DIM, SBP, CART, EXT>(a, b, blockIdx.x, blockIdx.y, sh);
+}
+
+// a work list of links (LinkJob, ordered by first chunk): chunk blockIdx.x
+// of the concatenated chunk lists, slot blockIdx.y (workgroups past a link's
+// slot count leave at once)
+template <int DIM, int SBP, int CART, int EXT>
+__global__ void __launch_bounds__(256) k_donor_blocks(const LinkJob *__restrict__ jobs, int njobs)
+{
+    extern __shared__ double sh[];
+    const int bx = blockIdx.x;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].chunk0 <= bx) lo = mid; else hi = mid - 1;
+    }
+    const LinkJob &J = jobs[lo];
+    if ((int)blockIdx.y >= J.a.nj) return;
+    donor_block_body<DIM, SBP, CART, EXT>(J.a, J.b, bx - J.chunk0, blockIdx.y, sh);
 }
 
 // extrapolated donor states at the donor-stencil points of mid-step links:
@@ -1316,6 +1370,63 @@ hipError_t launch_donor_block(const DonorLink &a, const DonorBlocks &b, hipStrea
     else if (g.dim == 2 && a.sbp == 42) DISPATCH_BLOCK(2, 42, 0);
     else if (g.dim == 3 && a.sbp == 21 && g.cartesian) DISPATCH_BLOCK(3, 21, 1);
     else if (g.dim == 3 && a.sbp == 42 && g.cartesian) DISPATCH_BLOCK(3, 42, 1);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <int TX, int TY, int TM>
+static hipError_t tiles_shape(const TileJob *jobs, int njobs, int nblk, int sbp, int cart, const Phys &ph,
+                              hipStream_t st)
+{
+    dim3 grid(nblk), blk(TX * TY * TM);
+    if (sbp == 21 && cart)
+        hipLaunchKernelGGL((k_rhs_tiles<21, 1, TX, TY, TM>), grid, blk, 0, st, jobs, njobs, nblk, ph);
+    else if (sbp == 21)
+        hipLaunchKernelGGL((k_rhs_tiles<21, 0, TX, TY, TM>), grid, blk, 0, st, jobs, njobs, nblk, ph);
+    else if (cart)
+        hipLaunchKernelGGL((k_rhs_tiles<42, 1, TX, TY, TM>), grid, blk, 0, st, jobs, njobs, nblk, ph);
+    else
+        hipLaunchKernelGGL((k_rhs_tiles<42, 0, TX, TY, TM>), grid, blk, 0, st, jobs, njobs, nblk, ph);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_tiles(const TileJob *jobs, int njobs, int nblk, int sbp, int cart, int shape, const Phys &ph,
+                            hipStream_t st)
+{
+    if (njobs <= 0 || nblk <= 0) return njobs == 0 ? hipSuccess : hipErrorInvalidValue;
+    switch (shape) {
+    case 0: return tiles_shape<32, 16, 1>(jobs, njobs, nblk, sbp, cart, ph, st);
+    case 1: return tiles_shape<16, 8, 1>(jobs, njobs, nblk, sbp, cart, ph, st);
+    case 2: return tiles_shape<16, 8, 2>(jobs, njobs, nblk, sbp, cart, ph, st);
+    case 3: return tiles_shape<16, 8, 4>(jobs, njobs, nblk, sbp, cart, ph, st);
+    case 4: return tiles_shape<32, 8, 1>(jobs, njobs, nblk, sbp, cart, ph, st);
+    case 5: return tiles_shape<32, 8, 2>(jobs, njobs, nblk, sbp, cart, ph, st);
+    case 6: return tiles_shape<16, 16, 1>(jobs, njobs, nblk, sbp, cart, ph, st);
+    case 7: return tiles_shape<16, 16, 2>(jobs, njobs, nblk, sbp, cart, ph, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+#define DISPATCH_BLOCKS(DIM, SBP, CART)                                                                  \
+    do {                                                                                                 \
+        if (ext)                                                                                         \
+            hipLaunchKernelGGL((k_donor_blocks<DIM, SBP, CART, 1>), grid, dim3(256), lds, st, jobs, njobs); \
+        else                                                                                             \
+            hipLaunchKernelGGL((k_donor_blocks<DIM, SBP, CART, 0>), grid, dim3(256), lds, st, jobs, njobs); \
+    } while (0)
+
+hipError_t launch_donor_blocks(const LinkJob *jobs, int njobs, int nchunk, int maxnj, int dim, int sbp, int cart,
+                               bool ext, size_t lds, hipStream_t st)
+{
+    if (njobs == 0 || nchunk == 0) return hipSuccess;
+    if (njobs < 0 || nchunk < 0 || maxnj < 1 || maxnj > MAXJ || lds > 64 * 1024) return hipErrorInvalidValue;
+    dim3 grid(nchunk, maxnj);
+    if (dim == 2 && sbp == 21 && cart) DISPATCH_BLOCKS(2, 21, 1);
+    else if (dim == 2 && sbp == 21) DISPATCH_BLOCKS(2, 21, 0);
+    else if (dim == 2 && sbp == 42 && cart) DISPATCH_BLOCKS(2, 42, 1);
+    else if (dim == 2 && sbp == 42) DISPATCH_BLOCKS(2, 42, 0);
+    else if (dim == 3 && sbp == 21 && cart) DISPATCH_BLOCKS(3, 21, 1);
+    else if (dim == 3 && sbp == 42 && cart) DISPATCH_BLOCKS(3, 42, 1);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

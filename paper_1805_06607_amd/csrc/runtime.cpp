@@ -6,10 +6,12 @@
 #include "kern.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -139,6 +141,8 @@ struct mr_ctx {
     std::vector<int> tgrid_of;                // grid of each timed launch
     bool two_pass = false;    // 2D: use the two-kernel (gradient pass) right-hand side
     bool donor_blocks = true; // one-launch donor data for links whose chunks fit one workgroup
+    int period = 1;                            // macrosteps after which every pointer repeats
+    int64_t version = 0;                       // bumped when a batch's launch plan must be rebuilt
     // macrosteps: one stream per grid, ordered by events (Order); -1: when
     // the grids hold at least kMultiStreamPoints points in all
     int multi_stream = -1;
@@ -146,6 +150,29 @@ struct mr_ctx {
     Order ord;
     EvSet eager;
     std::vector<hipEvent_t> ev;
+};
+
+// Many independent systems advanced together: per micro-time of the batch,
+// one work-list launch per kind of job (current donor data, fused 2D
+// right-hand sides, mid-step donor data) over every system that steps then.
+struct mr_batch {
+    std::vector<mr_ctx *> ctx;
+    hipStream_t st = nullptr;
+    int R = 1, P = 1;                  // micro-times per macrostep, macrosteps per plan period
+    size_t tj_cap = 0, lj_cap = 0, ws_bytes = 0;
+    mrk::TileJob *tj_d = nullptr;
+    mrk::LinkJob *lj_d = nullptr;
+    struct Launch {
+        int what;                      // 0 donor data at the current time, 1 right-hand sides, 2 mid-step donor data
+        int first, njobs, nblk, maxnj; // job range, workgroups (tiles or chunks), slots
+        int dim, sbp, cart, shape;
+        size_t lds;
+    };
+    std::vector<std::vector<Launch>> plan;   // [p * (R + 1) + k]
+    std::vector<int64_t> base, version;      // per system at the last plan build
+    int64_t steps = 0;                       // batch macrosteps since that build
+    bool built = false, bound = false;
+    std::string err;
 };
 
 namespace {
@@ -749,6 +776,69 @@ void free_evset(EvSet &e)
     e = EvSet{};
 }
 
+// ---- launch tables
+bool fused2d(const mr_ctx *c, const GridHost &g) { return g.dim == 2 && !c->two_pass; }
+
+int shape_of(const GridHost &g) { return g.tile >= 0 ? g.tile : mrk::default_tile_shape(g.dev); }
+
+// grid gi's evaluation at micro-time k as run_macrosteps issues it (after
+// its state swap, before its ring head advances)
+mrk::TileJob make_tile_job(const mr_ctx *c, int gi, int k)
+{
+    const GridHost &g = c->G[gi];
+    const int m = c->P.hist_len;
+    mrk::TileJob J{};
+    J.g = g.dev;
+    J.g.recv = recv_slice(c, g, k);
+    J.q = g.y[g.cur];
+    J.F = slot(c, g, 0);
+    J.cb.m = m;
+    for (int j = 0; j < m - 1; ++j) J.cb.hist[j] = slot(c, g, j + 1);
+    for (int j = 0; j < m; ++j) J.cb.c[j] = c->c_own[gi][j];
+    J.cb.y_next = g.y[1 - g.cur];
+    const mrk::TileShape &s = mrk::kTileShapes[shape_of(g)];
+    J.ntx = (g.n[0] + s.tx - 1) / s.tx;
+    J.nty = (g.n[1] + s.ty - 1) / s.ty;
+    return J;
+}
+
+mrk::LinkJob make_current_job(const mr_ctx *c, const Link &L, int k)
+{
+    mrk::LinkJob J{};
+    const GridHost &D = c->G[L.dg];
+    J.a = link_base(c, L);
+    J.a.nj = 1;
+    J.a.ys[0] = D.y[D.cur];
+    J.a.out[0] = recv_slice(c, c->G[L.rg], k);
+    J.b = link_blocks(L);
+    return J;
+}
+
+// the mid-step receiver rows a chunked link provides right after its donor
+// grid evaluated at micro-time k (its ring head already advanced)
+mrk::LinkJob make_future_job(const mr_ctx *c, const Link &L, int k)
+{
+    mrk::LinkJob J{};
+    const GridHost &D = c->G[L.dg];
+    const GridHost &R = c->G[L.rg];
+    const int m = c->P.hist_len, per_d = c->rmax / D.rate, per_g = c->rmax / R.rate;
+    J.a = link_base(c, L);
+    J.a.nj = 0;
+    J.a.m = m;
+    for (int j = 0; j < m; ++j) J.a.hist[j] = slot(c, D, j);
+    for (int jp = 1; jp < per_d; ++jp) {
+        int kp = k + jp;
+        if (kp > c->rmax) kp -= c->rmax;
+        if (kp % per_g) continue;
+        J.a.ys[J.a.nj] = D.y[D.cur];
+        for (int j = 0; j < m; ++j) J.a.beta[J.a.nj][j] = c->beta[L.dg][jp][j];
+        J.a.out[J.a.nj] = recv_slice(c, R, kp);
+        J.a.nj++;
+    }
+    J.b = link_blocks(L);
+    return J;
+}
+
 // per-grid streams (default priority, not synchronising with the null
 // stream) and their events, created on first use
 int ensure_streams(mr_ctx *c)
@@ -869,6 +959,161 @@ int set_macrostep(mr_ctx *c, double Hm)
             for (int j = 0; j < m; ++j) c->beta[g][jp][j] = (double)c->alpha_mid[g][jp][j] * Hg;
     }
     return MR_OK;
+}
+
+// ---- batches
+int bfail(mr_batch *b, int code, const char *msg)
+{
+    if (b) b->err = msg;
+    return code;
+}
+
+#define BHIPCHK(b, call)                                                                   \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) return bfail(b, MR_ERR_HIP, hipGetErrorString(e_));          \
+    } while (0)
+
+// one system's bookkeeping for its micro-time ks (state swaps, ring heads)
+// while collecting its jobs of that micro-time
+void batch_collect(const mr_ctx *c, int ks, std::vector<mrk::LinkJob> &cur, std::vector<mrk::TileJob> &tiles,
+                   std::vector<int> &tile_shape, std::vector<mrk::LinkJob> &fut)
+{
+    mr_ctx *cc = const_cast<mr_ctx *>(c);
+    const int G = (int)c->G.size(), m = c->P.hist_len;
+    bool ends[mrk::MAXG] = {};
+    for (int g = 0; g < G; ++g) {
+        ends[g] = ks % (c->rmax / c->G[g].rate) == 0;
+        if (ends[g]) cc->G[g].cur ^= 1;
+    }
+    for (const Link &L : c->links)
+        if (ends[L.rg] && ends[L.dg]) cur.push_back(make_current_job(c, L, ks));
+    for (int g = 0; g < G; ++g) {
+        if (!ends[g]) continue;
+        tiles.push_back(make_tile_job(c, g, ks));
+        tile_shape.push_back(shape_of(c->G[g]));
+        cc->G[g].head = (cc->G[g].head + 1) % m;
+    }
+    for (const Link &L : c->links) {
+        const GridHost &D = c->G[L.dg];
+        if (!ends[L.dg] || c->rmax / D.rate == 1 || D.closure.empty()) continue;
+        mrk::LinkJob J = make_future_job(c, L, ks);
+        if (J.a.nj) fut.push_back(J);
+    }
+}
+
+// group jobs of one kind by launch key, give each its offset in the
+// concatenated list, append to the host tables and record the launches
+template <class Job, class Key, class Count>
+void batch_group(std::vector<Job> &jobs, Key key, Count count, int what, std::vector<Job> &table,
+                 std::vector<mr_batch::Launch> &out)
+{
+    std::vector<std::array<int, 5>> keys;
+    for (auto &j : jobs) {
+        auto kk = key(j);
+        if (std::find(keys.begin(), keys.end(), kk) == keys.end()) keys.push_back(kk);
+    }
+    for (auto &kk : keys) {
+        mr_batch::Launch L{};
+        L.what = what;
+        L.first = (int)table.size();
+        L.dim = kk[0];
+        L.sbp = kk[1];
+        L.cart = kk[2];
+        L.shape = kk[3];
+        int off = 0;
+        for (auto &j : jobs) {
+            if (key(j) != kk) continue;
+            Job x = j;
+            count(x, off, L);
+            table.push_back(x);
+            L.njobs++;
+        }
+        L.nblk = off;
+        out.push_back(L);
+    }
+}
+
+int batch_build(mr_batch *b)
+{
+    const int n = (int)b->ctx.size();
+    std::vector<mrk::TileJob> tj;
+    std::vector<mrk::LinkJob> lj;
+    b->plan.assign((size_t)b->P * (b->R + 1), {});
+    std::vector<std::vector<std::pair<int, int>>> saved(n);
+    for (int s = 0; s < n; ++s)
+        for (auto &g : b->ctx[s]->G) saved[s].push_back({g.cur, g.head});
+    for (int p = 0; p < b->P; ++p)
+        for (int k = 1; k <= b->R; ++k) {
+            std::vector<mrk::LinkJob> cur, fut;
+            std::vector<mrk::TileJob> tiles;
+            std::vector<int> shapes;
+            for (int s = 0; s < n; ++s) {
+                const mr_ctx *c = b->ctx[s];
+                if ((k * c->rmax) % b->R) continue;
+                batch_collect(c, k * c->rmax / b->R, cur, tiles, shapes, fut);
+            }
+            // a tile job's tile0 carries its tile shape until the jobs are
+            // grouped by launch key; grouping then sets the real offsets
+            for (size_t i = 0; i < tiles.size(); ++i) tiles[i].tile0 = shapes[i];
+            auto &out = b->plan[(size_t)p * (b->R + 1) + k];
+            auto lkey = [&](const mrk::LinkJob &j) {
+                return std::array<int, 5>{j.a.g.dim, j.a.sbp, j.a.g.cartesian, 0, 0};
+            };
+            auto lcount = [&](mrk::LinkJob &j, int &off, mr_batch::Launch &L) {
+                j.chunk0 = off;
+                off += j.b.nchunk;
+                L.maxnj = std::max(L.maxnj, j.a.nj);
+                L.lds = std::max(L.lds, mrk::donor_block_lds(j.a.g.dim, j.b.maxu, L.what == 2 ? j.b.maxc : 0));
+            };
+            auto tkey = [&](const mrk::TileJob &j) {
+                return std::array<int, 5>{2, 0, j.g.cartesian, j.tile0, 0};
+            };
+            auto tcount = [&](mrk::TileJob &j, int &off, mr_batch::Launch &L) {
+                j.tile0 = off;
+                off += j.ntx * j.nty;
+                L.maxnj = 1;
+            };
+            batch_group(cur, lkey, lcount, 0, lj, out);
+            batch_group(tiles, tkey, tcount, 1, tj, out);
+            batch_group(fut, lkey, lcount, 2, lj, out);
+            for (auto &L : out)
+                if (L.what == 1) L.sbp = b->ctx[0]->P.sbp;
+        }
+    for (int s = 0; s < n; ++s)
+        for (size_t g = 0; g < b->ctx[s]->G.size(); ++g) {
+            b->ctx[s]->G[g].cur = saved[s][g].first;
+            b->ctx[s]->G[g].head = saved[s][g].second;
+        }
+    if (tj.size() > b->tj_cap || lj.size() > b->lj_cap) return bfail(b, MR_ERR_STATE, "launch plan exceeds the workspace");
+    if (!tj.empty())
+        BHIPCHK(b, hipMemcpyAsync(b->tj_d, tj.data(), tj.size() * sizeof(mrk::TileJob), hipMemcpyHostToDevice, b->st));
+    if (!lj.empty())
+        BHIPCHK(b, hipMemcpyAsync(b->lj_d, lj.data(), lj.size() * sizeof(mrk::LinkJob), hipMemcpyHostToDevice, b->st));
+    BHIPCHK(b, hipStreamSynchronize(b->st));
+    b->base.resize(n);
+    b->version.resize(n);
+    for (int s = 0; s < n; ++s) {
+        b->base[s] = b->ctx[s]->nmacro;
+        b->version[s] = b->ctx[s]->version;
+    }
+    b->steps = 0;
+    b->built = true;
+    return MR_OK;
+}
+
+// a system's bookkeeping of one macrostep (what run_macrosteps leaves behind)
+void advance_one(mr_ctx *c)
+{
+    const int m = c->P.hist_len;
+    for (int k = 1; k <= c->rmax; ++k)
+        for (auto &g : c->G)
+            if (k % (c->rmax / g.rate) == 0) {
+                g.cur ^= 1;
+                g.head = (g.head + 1) % m;
+            }
+    c->t += c->H;
+    c->nmacro++;
 }
 
 }  // namespace
@@ -1002,7 +1247,10 @@ int mr_finalize(mr_ctx *c, size_t *bytes)
     for (auto &g : c->G)
         if (c->rmax % g.rate) return fail(c, MR_ERR_SETUP, "rate %d does not divide %d", g.rate, c->rmax);
     int n = c->P.order, m = c->P.hist_len;
-
+    // a grid's ring head returns after m / gcd(m, rate) macrosteps, its
+    // state double buffer after 2 / gcd(2, rate)
+    c->period = 1;
+    for (auto &g : c->G) c->period = std::lcm(c->period, std::lcm(m / std::gcd(m, g.rate), 2 / std::gcd(2, g.rate)));
     c->alpha_own.assign(c->G.size(), {});
     c->alpha_mid.assign(c->G.size(), {});
     for (size_t g = 0; g < c->G.size(); ++g) {
@@ -1145,6 +1393,7 @@ int mr_receiver_data(mr_ctx *c, int g, const double *const *q, double *out)
 
 int mr_timestep(mr_ctx *c, double *h, double *H)
 {
+    if (c) c->version++;
     if (!c) return MR_ERR_ARG;
     if (!c->bound) return fail(c, MR_ERR_STATE, "mr_timestep before mr_bind_workspace");
     double Hm;
@@ -1173,6 +1422,7 @@ int mr_timestep(mr_ctx *c, double *h, double *H)
 
 int mr_mrab_start(mr_ctx *c, double t0)
 {
+    if (c) c->version++;
     if (!c) return MR_ERR_ARG;
     if (!c->bound) return fail(c, MR_ERR_STATE, "mr_mrab_start before mr_bind_workspace");
     if (!c->have_dt) {
@@ -1253,6 +1503,7 @@ int mr_mrab_macrostep(mr_ctx *c, int nsteps)
 
 int mr_set_macrostep(mr_ctx *c, double H)
 {
+    if (c) c->version++;
     if (!c) return MR_ERR_ARG;
     if (!c->finalized) return fail(c, MR_ERR_STATE, "mr_set_macrostep before mr_finalize");
     int rc = set_macrostep(c, H);
@@ -1273,6 +1524,7 @@ int mr_set_history(mr_ctx *c, int g, int j, const double *in)
 
 int mr_mrab_resume(mr_ctx *c, double t)
 {
+    if (c) c->version++;
     if (!c) return MR_ERR_ARG;
     if (!c->started) return fail(c, MR_ERR_STATE, "mr_mrab_resume before mr_mrab_start");
     int rc = restage(c);
@@ -1349,6 +1601,7 @@ int mr_kernel_time(mr_ctx *c, double *total_ms, int *count) { return mr_kernel_t
 
 int mr_set_option(mr_ctx *c, const char *name, int64_t value)
 {
+    if (c) c->version++;
     if (!c || !name) return MR_ERR_ARG;
     if (!strcmp(name, "rhs_two_pass")) {
         if (value != 0 && value != 1) return fail(c, MR_ERR_ARG, "rhs_two_pass must be 0 or 1");
@@ -1370,6 +1623,7 @@ int mr_set_option(mr_ctx *c, const char *name, int64_t value)
 
 int mr_set_tile_shape(mr_ctx *c, int g, int shape)
 {
+    if (c) c->version++;
     if (!c || g < 0 || g >= (int)c->G.size() || shape < -1 || shape >= mrk::NUM_TILE_SHAPES) return MR_ERR_ARG;
     if (c->G[g].dim != 2) return fail(c, MR_ERR_UNSUPPORTED, "tile shapes apply to 2D grids");
     c->G[g].tile = shape;
@@ -1392,6 +1646,7 @@ int mr_get_tile_shape(const mr_ctx *c, int g, int *shape, int *tx, int *ty, int 
 
 int mr_autotune(mr_ctx *c, int reps)
 {
+    if (c) c->version++;
     if (!c || reps < 1 || reps > 1000) return MR_ERR_ARG;
     if (!c->bound) return fail(c, MR_ERR_STATE, "mr_autotune before mr_bind_workspace");
     if (c->two_pass) return MR_OK;
@@ -1448,6 +1703,105 @@ int mr_guard(mr_ctx *c, double *maxabs)
     if (maxabs) *maxabs = mx;
     if (!std::isfinite(mx)) return fail(c, MR_ERR_NONFINITE, "non-finite value in a state");
     return MR_OK;
+}
+
+int mr_batch_create(mr_ctx *const *ctxs, int n, mr_batch **out)
+{
+    if (!ctxs || n < 1 || !out) return MR_ERR_ARG;
+    *out = nullptr;
+    for (int s = 0; s < n; ++s) {
+        const mr_ctx *c = ctxs[s];
+        if (!c || !c->finalized) return MR_ERR_STATE;
+        if (c->P.dim != 2 || c->two_pass || c->P.sbp != ctxs[0]->P.sbp || c->st != ctxs[0]->st)
+            return MR_ERR_UNSUPPORTED;
+        for (const Link &L : c->links)
+            if (!use_blocks(c, L)) return MR_ERR_UNSUPPORTED;
+        for (int t = 0; t < s; ++t)
+            if (ctxs[t] == c) return MR_ERR_ARG;
+    }
+    mr_batch *b = new mr_batch();
+    b->ctx.assign(ctxs, ctxs + n);
+    b->st = ctxs[0]->st;
+    for (auto *c : b->ctx) {
+        b->R = std::lcm(b->R, c->rmax);
+        b->P = std::lcm(b->P, c->period);
+    }
+    if (b->R > 64 || b->P > 4096) {
+        delete b;
+        return MR_ERR_UNSUPPORTED;
+    }
+    size_t nt = 0, nl = 0;
+    for (auto *c : b->ctx) {
+        for (auto &g : c->G) nt += g.rate;
+        nl += c->links.size() * 2 * c->rmax;
+    }
+    b->tj_cap = (size_t)b->P * nt;
+    b->lj_cap = (size_t)b->P * nl;
+    b->ws_bytes = (b->tj_cap * sizeof(mrk::TileJob) + ALIGN) / ALIGN * ALIGN + b->lj_cap * sizeof(mrk::LinkJob) + ALIGN;
+    *out = b;
+    return MR_OK;
+}
+
+int mr_batch_workspace_size(const mr_batch *b, size_t *bytes)
+{
+    if (!b || !bytes) return MR_ERR_ARG;
+    *bytes = b->ws_bytes;
+    return MR_OK;
+}
+
+int mr_batch_bind_workspace(mr_batch *b, void *dev, size_t bytes)
+{
+    if (!b || !dev) return MR_ERR_ARG;
+    if (bytes < b->ws_bytes) return bfail(b, MR_ERR_ARG, "workspace too small");
+    if ((uintptr_t)dev % ALIGN) return bfail(b, MR_ERR_ARG, "workspace not 256-byte aligned");
+    char *base = (char *)dev;
+    b->tj_d = reinterpret_cast<mrk::TileJob *>(base);
+    size_t off = (b->tj_cap * sizeof(mrk::TileJob) + ALIGN) / ALIGN * ALIGN;
+    b->lj_d = reinterpret_cast<mrk::LinkJob *>(base + off);
+    b->bound = true;
+    b->built = false;
+    return MR_OK;
+}
+
+int mr_batch_macrostep(mr_batch *b, int nsteps)
+{
+    if (!b || nsteps < 0) return MR_ERR_ARG;
+    if (!b->bound) return bfail(b, MR_ERR_STATE, "mr_batch_macrostep before mr_batch_bind_workspace");
+    const int n = (int)b->ctx.size();
+    bool rebuild = !b->built;
+    for (int s = 0; s < n; ++s) {
+        const mr_ctx *c = b->ctx[s];
+        if (!c->started || c->stale) return bfail(b, MR_ERR_STATE, "a system is not started (or needs mr_mrab_resume)");
+        if (b->built && (c->version != b->version[s] || c->nmacro != b->base[s] + b->steps)) rebuild = true;
+    }
+    if (rebuild) {
+        int rc = batch_build(b);
+        if (rc) return rc;
+    }
+    for (int it = 0; it < nsteps; ++it) {
+        const int p = (int)(b->steps % b->P);
+        for (int k = 1; k <= b->R; ++k)
+            for (const auto &L : b->plan[(size_t)p * (b->R + 1) + k]) {
+                if (L.what == 1)
+                    BHIPCHK(b, mrk::launch_rhs_tiles(b->tj_d + L.first, L.njobs, L.nblk, L.sbp, L.cart, L.shape,
+                                                     b->ctx[0]->ph, b->st));
+                else
+                    BHIPCHK(b, mrk::launch_donor_blocks(b->lj_d + L.first, L.njobs, L.nblk, L.maxnj, L.dim, L.sbp,
+                                                        L.cart, L.what == 2, L.lds, b->st));
+            }
+        for (auto *c : b->ctx) advance_one(c);
+        b->steps++;
+    }
+    return MR_OK;
+}
+
+const char *mr_batch_last_error(const mr_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+void mr_batch_destroy(mr_batch *b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->st);
+    delete b;
 }
 
 const char *mr_last_error(const mr_ctx *c) { return c ? c->err.c_str() : "null context"; }

@@ -1,0 +1,77 @@
+"""Batched systems (C ABI mr_batch_*) against each system stepped on its own:
+the same work-list kernels' per-tile and per-chunk code, so every system's
+states and histories are bitwise those of its own macrosteps."""
+import sys
+
+import pytest
+
+import workloads
+from gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _systems(wls):
+    from paper_1805_06607_amd.system import System
+    out = []
+    for wl in wls:
+        s = System(wl)
+        s.timestep()
+        s.start(0.0)
+        out.append(s)
+    return out
+
+
+def _snap(s):
+    m = s.wl.params["hist_len"]
+    return [s.state(g).clone() for g in range(s.ngrids)] + \
+        [s.history(g, j).clone() for g in range(s.ngrids) for j in range(m)]
+
+
+def test_batch_bitwise_equals_individual(torch):
+    from paper_1805_06607_amd.batch import Batch
+    wls = workloads.batch_vortex(6, seed=5, smin=24, smax=48)
+    _say("systems", [(w.grids[0].n[0], w.grids[1].n[0], w.grids[1].rate) for w in wls])
+    solo = _systems(wls)
+    grouped = _systems(workloads.batch_vortex(6, seed=5, smin=24, smax=48))
+    b = Batch(grouped)
+    for n in (1, 5, 12, 7):
+        b.macrostep(n)
+        for s in solo:
+            s.macrostep(n)
+        torch.cuda.synchronize()
+        for i, (a, c) in enumerate(zip(solo, grouped)):
+            assert a.time() == c.time(), (n, i)
+            for x, y in zip(_snap(a), _snap(c)):
+                assert torch.equal(x, y), (n, i)
+        _say("after", n, "macrosteps: bitwise equal")
+    # a system stepped on its own in between: the batch rebuilds its plan
+    solo[2].macrostep(3)
+    grouped[2].macrostep(3)
+    b.macrostep(4)
+    for s in solo:
+        s.macrostep(4)
+    torch.cuda.synchronize()
+    for a, c in zip(solo, grouped):
+        for x, y in zip(_snap(a), _snap(c)):
+            assert torch.equal(x, y)
+    b.close()
+
+
+def test_batch_rejects_unsupported(torch):
+    from paper_1805_06607_amd import _lib
+    from paper_1805_06607_amd.batch import Batch
+    mixed = _systems([workloads.vortex_box(nbg=32, npatch=16),
+                      workloads.cylinder(nbg=96, ntheta=64, nr=32, half=6.0)])
+    with pytest.raises(_lib.MrabError):
+        Batch(mixed)

@@ -138,26 +138,31 @@ def vortex_state(x, y, t, gamma, omega, phi, x0, y0, u0, v0):
 
 
 def vortex_box(nbg: int = 64, npatch: int = 32, Re: float = 1000.0, rate_bg: int = 1,
-               rate_patch: int = 2, order: int = 3) -> Workload:
+               rate_patch: int = 2, order: int = 3, spacing: Optional[float] = None,
+               centre: Optional[Sequence[float]] = None) -> Workload:
     """Periodic 64^2 background on [0,10)^2 with a 32^2 patch at half spacing.
 
     The patch is centred on an isentropic vortex (strength 5, advected at
     Mach 0.5).  SBP 2-1, bilinear donors, third-order MRAB with ratio 2.
+    spacing (default 10 / nbg) sets the background spacing, so the periodic
+    domain is nbg * spacing wide; centre (default the domain centre) places
+    the vortex and the patch.
     """
     gamma = 1.4
-    L = 10.0
-    h = L / nbg
+    h = 10.0 / nbg if spacing is None else spacing
+    L = nbg * h
     hp = h / 2.0
-    c = 5.0
+    cx, cy = (0.5 * L, 0.5 * L) if centre is None else centre
+    c = cx
     half_patch = 0.5 * (npatch - 1) * hp
     g0 = Grid("background", (nbg, nbg), (True, True), CARTESIAN,
               [BC_PERIODIC] * 4, rate_bg, 0, origin=(0.0, 0.0, 0.0), spacing=(h, h, h))
     # hole: the patch box shrunk by four patch cells
     hh = half_patch - 4.0 * hp
-    g0.holes.append(("box", (c - hh, c - hh), (c + hh, c + hh)))
+    g0.holes.append(("box", (cx - hh, cy - hh), (cx + hh, cy + hh)))
     g1 = Grid("patch", (npatch, npatch), (False, False), CARTESIAN,
               [BC_INTERFACE] * 4, rate_patch, 1,
-              origin=(c - half_patch, c - half_patch, 0.0), spacing=(hp, hp, hp))
+              origin=(cx - half_patch, cy - half_patch, 0.0), spacing=(hp, hp, hp))
     params = default_params(gamma=gamma, Re=Re, sbp=21, order=order, hist_len=order,
                             interp_width=2, cfl=0.5)
     u0 = 0.5 * math.sqrt(gamma)
@@ -166,10 +171,30 @@ def vortex_box(nbg: int = 64, npatch: int = 32, Re: float = 1000.0, rate_bg: int
     q0 = []
     for g in (g0, g1):
         X = g.points()
-        rho, u, v, p = vortex_state(X[0], X[1], 0.0, gamma, 5.0, 1.0, c, c, u0, 0.0)
+        rho, u, v, p = vortex_state(X[0], X[1], 0.0, gamma, 5.0, 1.0, cx, cy, u0, 0.0)
         q0.append(conserved_from_primitive(rho, [u, v], p, gamma))
     return Workload("vortex_box", 2, params, [g0, g1], q0, macrosteps=100,
                     notes="isentropic vortex box-in-box, SBP 2-1, bilinear, AB3 ratio 2")
+
+
+def batch_vortex(nsys: int = 64, seed: int = 3, smin: int = 64, smax: int = 512,
+                 spacing: float = 10.0 / 64.0, rates: Sequence[int] = (1, 2, 4)) -> List[Workload]:
+    """Independent vortex systems of uneven size: background side
+    S ~ U{smin..smax} at a common spacing, patch side ~ U{ceil(S/4)..floor(S/2)}
+    at half spacing centred on a seeded vortex position (kept clear of the
+    periodic seam), patch rate drawn from `rates`; AB3."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(nsys):
+        S = int(rng.integers(smin, smax + 1))
+        P = int(rng.integers(-(-S // 4), S // 2 + 1))
+        r = int(rng.choice(np.asarray(rates)))
+        L = S * spacing
+        half = 0.5 * (P - 1) * spacing / 2.0
+        lo, hi = half + 2.0 * spacing, L - half - 2.0 * spacing
+        cx, cy = (float(rng.uniform(lo, hi)), float(rng.uniform(lo, hi)))
+        out.append(vortex_box(nbg=S, npatch=P, rate_patch=r, spacing=spacing, centre=(cx, cy)))
+    return out
 
 
 # ----------------------------------------------------------------------------
