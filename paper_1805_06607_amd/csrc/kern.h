@@ -83,6 +83,15 @@ struct DonorBlocks {
     int nchunk, rpc, maxu, maxc;
 };
 
+// two 2D links' donor data in one launch by value: link i owns chunks
+// chunk0[i] .. chunk0[i+1] - 1
+struct DonorLinks2 {
+    DonorLink a[2];
+    DonorBlocks b[2];
+    int chunk0[3];
+    int n;
+};
+
 // one link's donor data in a work-list launch (chunks chunk0 .. chunk0 +
 // b.nchunk - 1 of the concatenated list)
 struct LinkJob {
@@ -112,6 +121,7 @@ hipError_t launch_rhs(const GridDev &g, const GridDev *g_dev, int sbp, const Phy
 hipError_t launch_donor(const DonorLink &a, hipStream_t st);
 // one launch: (extrapolation when a.m > 0,) values and gather per chunk
 hipError_t launch_donor_block(const DonorLink &a, const DonorBlocks &b, hipStream_t st);
+hipError_t launch_donor_block2(const DonorLinks2 &links, hipStream_t st);
 size_t donor_block_lds(int dim, int maxu, int maxc);
 hipError_t launch_extrap(const Extrap &a, hipStream_t st);
 // fused LDS-tiled 2D right-hand side (gradients, fluxes, divergence, SAT, AB update)

@@ -984,7 +984,14 @@ __device__ __forceinline__ void donor_block_body(const DonorLink &a, const Donor
         int ic[3];
         coords(a.g, p, ic);
         double gr[DIM + 1][DIM];
-        gradient<DIM, SBP, CART>(a.g, p, ic, a.ph.gamma - 1.0, qload, gr);
+        if constexpr (CART == 2) {          // grid kind chosen per link at run time
+            if (a.g.cartesian)
+                gradient<DIM, SBP, 1>(a.g, p, ic, a.ph.gamma - 1.0, qload, gr);
+            else
+                gradient<DIM, SBP, 0>(a.g, p, ic, a.ph.gamma - 1.0, qload, gr);
+        } else {
+            gradient<DIM, SBP, CART>(a.g, p, ic, a.ph.gamma - 1.0, qload, gr);
+        }
         double u_[DIM];
         double ri = 1.0 / qp[0];
 #pragma unroll
@@ -1031,6 +1038,17 @@ __global__ void __launch_bounds__(256) k_donor_block(DonorLink a, DonorBlocks b)
 {
     extern __shared__ double sh[];
     donor_block_body<DIM, SBP, CART, EXT>(a, b, blockIdx.x, blockIdx.y, sh);
+}
+
+// up to two links by value in one launch (their grid kinds may differ):
+// chunk blockIdx.x of the two chunk lists, slot blockIdx.y
+template <int DIM, int SBP, int EXT>
+__global__ void __launch_bounds__(256) k_donor_block2(DonorLinks2 L)
+{
+    extern __shared__ double sh[];
+    const int w = (L.n > 1 && (int)blockIdx.x >= L.chunk0[1]) ? 1 : 0;
+    if ((int)blockIdx.y >= L.a[w].nj) return;
+    donor_block_body<DIM, SBP, 2, EXT>(L.a[w], L.b[w], blockIdx.x - L.chunk0[w], blockIdx.y, sh);
 }
 
 // a work list of links (LinkJob, ordered by first chunk): chunk blockIdx.x
@@ -1364,10 +1382,10 @@ hipError_t launch_donor_block(const DonorLink &a, const DonorBlocks &b, hipStrea
     const GridDev &g = a.g;
     size_t lds = donor_block_lds(g.dim, b.maxu, ext ? b.maxc : 0);
     dim3 grid(b.nchunk, a.nj);
-    if (g.dim == 2 && a.sbp == 21 && g.cartesian) DISPATCH_BLOCK(2, 21, 1);
-    else if (g.dim == 2 && a.sbp == 21) DISPATCH_BLOCK(2, 21, 0);
-    else if (g.dim == 2 && a.sbp == 42 && g.cartesian) DISPATCH_BLOCK(2, 42, 1);
-    else if (g.dim == 2 && a.sbp == 42) DISPATCH_BLOCK(2, 42, 0);
+    // 2D: one body for both grid kinds (chosen per link at run time), so
+    // every launch form runs the same code on a link
+    if (g.dim == 2 && a.sbp == 21) DISPATCH_BLOCK(2, 21, 2);
+    else if (g.dim == 2 && a.sbp == 42) DISPATCH_BLOCK(2, 42, 2);
     else if (g.dim == 3 && a.sbp == 21 && g.cartesian) DISPATCH_BLOCK(3, 21, 1);
     else if (g.dim == 3 && a.sbp == 42 && g.cartesian) DISPATCH_BLOCK(3, 42, 1);
     else return hipErrorInvalidValue;
@@ -1421,13 +1439,38 @@ hipError_t launch_donor_blocks(const LinkJob *jobs, int njobs, int nchunk, int m
     if (njobs == 0 || nchunk == 0) return hipSuccess;
     if (njobs < 0 || nchunk < 0 || maxnj < 1 || maxnj > MAXJ || lds > 64 * 1024) return hipErrorInvalidValue;
     dim3 grid(nchunk, maxnj);
-    if (dim == 2 && sbp == 21 && cart) DISPATCH_BLOCKS(2, 21, 1);
-    else if (dim == 2 && sbp == 21) DISPATCH_BLOCKS(2, 21, 0);
-    else if (dim == 2 && sbp == 42 && cart) DISPATCH_BLOCKS(2, 42, 1);
-    else if (dim == 2 && sbp == 42) DISPATCH_BLOCKS(2, 42, 0);
+    (void)cart;
+    if (dim == 2 && sbp == 21) DISPATCH_BLOCKS(2, 21, 2);
+    else if (dim == 2 && sbp == 42) DISPATCH_BLOCKS(2, 42, 2);
     else if (dim == 3 && sbp == 21 && cart) DISPATCH_BLOCKS(3, 21, 1);
     else if (dim == 3 && sbp == 42 && cart) DISPATCH_BLOCKS(3, 42, 1);
     else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_donor_block2(const DonorLinks2 &L, hipStream_t st)
+{
+    if (L.n < 1 || L.n > 2) return hipErrorInvalidValue;
+    int nj = 0, dim = L.a[0].g.dim, sbp = L.a[0].sbp, chunks = L.chunk0[L.n];
+    bool ext = L.a[0].m > 0;
+    size_t lds = 0;
+    for (int i = 0; i < L.n; ++i) {
+        const DonorLink &a = L.a[i];
+        const DonorBlocks &b = L.b[i];
+        if (a.g.dim != dim || a.sbp != sbp || (a.m > 0) != ext || a.S < 1 || a.S > 64 || (a.S & (a.S - 1)) ||
+            b.rpc * a.S > 256 || a.nj < 1 || a.nj > MAXJ || (int64_t)b.nchunk * b.rpc < a.nrecv ||
+            L.chunk0[i + 1] - L.chunk0[i] != b.nchunk)
+            return hipErrorInvalidValue;
+        nj = a.nj > nj ? a.nj : nj;
+        size_t s = donor_block_lds(dim, b.maxu, ext ? b.maxc : 0);
+        lds = s > lds ? s : lds;
+    }
+    if (dim != 2 || lds > 64 * 1024) return hipErrorInvalidValue;
+    dim3 grid(chunks, nj);
+    if (sbp == 21 && ext) hipLaunchKernelGGL((k_donor_block2<2, 21, 1>), grid, dim3(256), lds, st, L);
+    else if (sbp == 21) hipLaunchKernelGGL((k_donor_block2<2, 21, 0>), grid, dim3(256), lds, st, L);
+    else if (ext) hipLaunchKernelGGL((k_donor_block2<2, 42, 1>), grid, dim3(256), lds, st, L);
+    else hipLaunchKernelGGL((k_donor_block2<2, 42, 0>), grid, dim3(256), lds, st, L);
     return hipGetLastError();
 }
 

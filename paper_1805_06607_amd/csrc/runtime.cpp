@@ -619,6 +619,28 @@ int link_current(mr_ctx *c, const Link &L, const double *y, double *out, int si,
     return MR_OK;
 }
 
+// current-time donor data of one or two chunked 2D links in one launch
+// (context stream): each from its donor grid's current state into its
+// receiving grid's rows of micro-time k
+int links_current2(mr_ctx *c, const std::vector<const Link *> &ls, int k)
+{
+    mrk::DonorLinks2 P{};
+    P.n = (int)ls.size();
+    P.chunk0[0] = 0;
+    for (int i = 0; i < P.n; ++i) {
+        const Link &L = *ls[i];
+        const GridHost &D = c->G[L.dg];
+        P.a[i] = link_base(c, L);
+        P.a[i].nj = 1;
+        P.a[i].ys[0] = D.y[D.cur];
+        P.a[i].out[0] = recv_slice(c, c->G[L.rg], k);
+        P.b[i] = link_blocks(L);
+        P.chunk0[i + 1] = P.chunk0[i] + L.nchunk;
+    }
+    HIPCHK(c, mrk::launch_donor_block2(P, c->st));
+    return MR_OK;
+}
+
 // right after donor grid d evaluated at micro-time k: its extrapolant is
 // fixed until its next step, so the donor data of every later micro-time
 // k' < k + per_d at which a receiving grid evaluates is gathered now:
@@ -877,12 +899,27 @@ int run_macrosteps(mr_ctx *c, int nsteps, bool ms, hipStream_t origin, const EvS
                 ends[g] = k % (c->rmax / c->G[g].rate) == 0;
                 if (ends[g]) c->G[g].cur ^= 1;   // the staged own step becomes current
             }
-            // donor data from donors at their own step; mid-step donor data
-            // was gathered right after the donor grid's last evaluation
+            // donor data from donors at their own step (on one stream, 2D
+            // chunked links two to a launch); mid-step donor data was
+            // gathered right after the donor grid's last evaluation
+            std::vector<const Link *> pair;
             for (const Link &L : c->links) {
                 if (!ends[L.rg] || !ends[L.dg]) continue;
                 const GridHost &D = c->G[L.dg];
+                if (!ms && D.dim == 2 && use_blocks(c, L)) {
+                    pair.push_back(&L);
+                    if (pair.size() == 2) {
+                        int rc = links_current2(c, pair, k);
+                        if (rc) return rc;
+                        pair.clear();
+                    }
+                    continue;
+                }
                 int rc = link_current(c, L, D.y[D.cur], recv_slice(c, c->G[L.rg], k), gsi(L.dg), k);
+                if (rc) return rc;
+            }
+            if (!pair.empty()) {
+                int rc = links_current2(c, pair, k);
                 if (rc) return rc;
             }
             for (int g = 0; g < G; ++g) {
