@@ -278,6 +278,12 @@ int mr_batch_create(mr_ctx *const *ctxs, int n, mr_batch **out);
 int mr_batch_workspace_size(const mr_batch *batch, size_t *bytes);
 int mr_batch_bind_workspace(mr_batch *batch, void *dev_ptr, size_t bytes);
 int mr_batch_macrostep(mr_batch *batch, int nsteps);
+/* Tile shape of every right-hand side in the batch's launches (0 ..
+ * MR_NUM_TILE_SHAPES-1), or -1 (default) for each grid's own shape, with
+ * which every system's result equals its own macrosteps bit for bit.  A
+ * batch fills the GPU with many grids at once, so large tiles (shape 0, 32 x
+ * 16) usually beat the small multi-thread tiles that suit one small grid. */
+int mr_batch_set_tile_shape(mr_batch *batch, int shape);
 const char *mr_batch_last_error(const mr_batch *batch);
 void mr_batch_destroy(mr_batch *batch);
 

@@ -72,6 +72,7 @@ SIGNATURES = {
     "mr_batch_workspace_size": [c_void_p, POINTER(c_size_t)],
     "mr_batch_bind_workspace": [c_void_p, c_void_p, c_size_t],
     "mr_batch_macrostep": [c_void_p, c_int],
+    "mr_batch_set_tile_shape": [c_void_p, c_int],
     "mr_batch_last_error": [c_void_p],
     "mr_batch_destroy": [c_void_p],
     "mr_last_error": [c_void_p],

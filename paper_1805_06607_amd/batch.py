@@ -34,6 +34,11 @@ class Batch:
             msg = self.lib.mr_batch_last_error(self.b).decode() if self.b else ""
             raise _lib.MrabError(f"{what}: {_lib.STATUS.get(rc, rc)} {msg}")
 
+    def set_tile_shape(self, shape: int):
+        """One tile shape for every right-hand side of the batch (-1: each
+        grid's own, which keeps every system bitwise equal to its own runs)."""
+        self._check(self.lib.mr_batch_set_tile_shape(self.b, shape), "mr_batch_set_tile_shape")
+
     def macrostep(self, n: int = 1):
         self._check(self.lib.mr_batch_macrostep(self.b, n), "mr_batch_macrostep")
 

@@ -74,12 +74,16 @@ struct DonorLink {
 // Receivers of a link cut into chunks of rpc consecutive receivers (rpc * S
 // = 256 entries), one workgroup per (chunk, slot): the chunk's distinct donor
 // points upts[ustart[c] .. ustart[c+1]) (sorted), each entry's index among
-// them (eloc, receiver-major), and the points their gradient stencils read,
+// them (eloc, receiver-major), the points their gradient stencils read,
 // cpts[cstart[c] .. cstart[c+1]) (sorted; used when the state is an
-// extrapolant).  Dynamic LDS: maxu * RB + maxc * nv doubles, maxc ints.
+// extrapolant), and per distinct donor point 1 + 4 dim positions in that
+// list (bpos, same indexing as upts times 1 + 4 dim): the point, then its
+// stencil in the order the gradient reads it (-1 past a short row).
+// Dynamic LDS: maxu * RB + maxc * nv doubles, and maxu * (1 + 4 dim) int16
+// when extrapolating.
 struct DonorBlocks {
     const int32_t *ustart, *upts, *cstart, *cpts;
-    const int16_t *eloc;
+    const int16_t *eloc, *bpos;
     int nchunk, rpc, maxu, maxc;
 };
 

@@ -907,9 +907,10 @@ __device__ __forceinline__ void donor_block_body(const DonorLink &a, const Donor
     constexpr int NV = DIM + 2;
     constexpr int RB = NV + DIM * (NV - 1);
     constexpr int NT = 256;
+    constexpr int KP = 1 + 4 * DIM;                    // stencil positions per donor point
     double *sV = sh;                                   // maxu x RB
     double *sQ = sh + (size_t)b.maxu * RB;             // NV x maxc
-    int32_t *sI = reinterpret_cast<int32_t *>(sQ + (size_t)b.maxc * NV);   // maxc
+    int16_t *sP = reinterpret_cast<int16_t *>(sQ + (size_t)b.maxc * NV);   // maxu x KP
     const int tid = threadIdx.x;
     const double *y = nullptr;
     double *outp = nullptr;
@@ -958,20 +959,21 @@ __device__ __forceinline__ void donor_block_body(const DonorLink &a, const Donor
                 for (int hh = 0; hh < MAXH; ++hh)
                     if (hh < mh) acc = add_nc(acc, bj[hh], lh[r][hh]);
                 sQ[(size_t)v * b.maxc + ii] = acc;
-                if (v == 0) sI[ii] = (int32_t)(el[r] - (int64_t)v * N);
             }
         }
+        for (int i = tid; i < nu * KP; i += NT) sP[i] = b.bpos[(size_t)u0 * KP + i];
         __syncthreads();
     }
+    // EXT: the point's own entry, then its gradient stencil in the order
+    // gradient() reads it (directions ascending, each row's offsets as the SBP
+    // row applies them), as positions in the chunk's extrapolated points
+    const int16_t *pos = nullptr;
+    int cursor = 0;
     auto qload = [&](int64_t idx, double *o) {
         if constexpr (EXT) {
-            int lo = 0, hi = nc;                       // first entry >= idx (present by construction)
-            while (lo < hi) {
-                int mid = (lo + hi) >> 1;
-                if (sI[mid] < idx) lo = mid + 1; else hi = mid;
-            }
+            const int at = pos[cursor++];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) o[v] = sQ[(size_t)v * b.maxc + lo];
+            for (int v = 0; v < NV; ++v) o[v] = sQ[(size_t)v * b.maxc + at];
         } else {
 #pragma unroll
             for (int v = 0; v < NV; ++v) o[v] = y[v * N + idx];
@@ -979,6 +981,8 @@ __device__ __forceinline__ void donor_block_body(const DonorLink &a, const Donor
     };
     for (int u = tid; u < nu; u += NT) {
         const int64_t p = b.upts[u0 + u];
+        pos = sP + (size_t)u * KP;
+        cursor = 0;
         double qp[NV];
         qload(p, qp);
         int ic[3];
@@ -1359,8 +1363,8 @@ hipError_t launch_donor(const DonorLink &a, hipStream_t st)
 
 size_t donor_block_lds(int dim, int maxu, int maxc)
 {
-    int nv = dim + 2, rb = nv + dim * (nv - 1);
-    return ((size_t)maxu * rb + (size_t)maxc * nv) * 8 + (size_t)maxc * 4;
+    int nv = dim + 2, rb = nv + dim * (nv - 1), kp = 1 + 4 * dim;
+    return ((size_t)maxu * rb + (size_t)maxc * nv) * 8 + (maxc ? (size_t)maxu * kp * 2 : 0);
 }
 
 #define DISPATCH_BLOCK(DIM, SBP, CART)                                                                   \

@@ -67,9 +67,9 @@ struct Link {
     bool blk = false;
     int nchunk = 0, rpc = 0, maxu = 0, maxc = 0;
     std::vector<int32_t> bus, bup, bcs, bcp;
-    std::vector<int16_t> bel;
+    std::vector<int16_t> bel, bpos;
     int32_t *bus_d = nullptr, *bup_d = nullptr, *bcs_d = nullptr, *bcp_d = nullptr;
-    int16_t *bel_d = nullptr;
+    int16_t *bel_d = nullptr, *bpos_d = nullptr;
 };
 
 // Cross-stream order inside one macrostep call.  Stream s (one per grid)
@@ -172,6 +172,7 @@ struct mr_batch {
     std::vector<int64_t> base, version;      // per system at the last plan build
     int64_t steps = 0;                       // batch macrosteps since that build
     bool built = false, bound = false;
+    int shape = -1;                          // tile shape of every right-hand side (-1: each grid's own)
     std::string err;
 };
 
@@ -393,6 +394,7 @@ void build_blocks(const mr_ctx *c, Link &L)
     L.bup.clear();
     L.bcp.clear();
     L.bel.assign((size_t)L.n * S, 0);
+    L.bpos.clear();
     L.maxu = L.maxc = 0;
     std::vector<int> off;
     for (int ch = 0; ch < L.nchunk; ++ch) {
@@ -422,6 +424,25 @@ void build_blocks(const mr_ctx *c, Link &L)
         }
         std::sort(C.begin(), C.end());
         C.erase(std::unique(C.begin(), C.end()), C.end());
+        // per distinct point: its position in C, then its stencil's, in the
+        // order the device gradient reads them
+        const int kp = 1 + 4 * D.dim;
+        auto at = [&](int64_t q) { return (int16_t)(std::lower_bound(C.begin(), C.end(), (int32_t)q) - C.begin()); };
+        for (int32_t p : U) {
+            std::vector<int16_t> row(kp, (int16_t)-1);
+            int t = 0;
+            row[t++] = at(p);
+            int ic[3] = {(int)(p % D.n[0]), (int)((p / D.n[0]) % D.n[1]), (int)(p / ((int64_t)D.n[0] * D.n[1]))};
+            for (int m = 0; m < D.dim; ++m) {
+                row_offsets(c->P.sbp, D.cls[(size_t)m * D.npts + p] & 15, off);
+                for (int o : off) {
+                    int j = ic[m] + o;
+                    if (D.periodic[m]) j = ((j % D.n[m]) + D.n[m]) % D.n[m];
+                    row[t++] = at(p + (int64_t)(j - ic[m]) * D.stride[m]);
+                }
+            }
+            L.bpos.insert(L.bpos.end(), row.begin(), row.end());
+        }
         L.maxu = std::max(L.maxu, (int)U.size());
         L.maxc = std::max(L.maxc, (int)C.size());
         L.bup.insert(L.bup.end(), U.begin(), U.end());
@@ -483,6 +504,7 @@ size_t layout(mr_ctx *c, char *base)
         L.bup_d = cv.take<int32_t>(L.bup.size() + 1);
         L.bcp_d = cv.take<int32_t>(L.bcp.size() + 1);
         L.bel_d = cv.take<int16_t>(L.bel.size() + 1);
+        L.bpos_d = cv.take<int16_t>(L.bpos.size() + 1);
     }
     c->grids_d = cv.take<GridDev>(c->G.size());
     c->partial = cv.take<double>(1024);
@@ -588,6 +610,7 @@ mrk::DonorBlocks link_blocks(const Link &L)
     b.cstart = L.bcs_d;
     b.cpts = L.bcp_d;
     b.eloc = L.bel_d;
+    b.bpos = L.bpos_d;
     b.nchunk = L.nchunk;
     b.rpc = L.rpc;
     b.maxu = L.maxu;
@@ -1090,6 +1113,13 @@ int batch_build(mr_batch *b)
                 if ((k * c->rmax) % b->R) continue;
                 batch_collect(c, k * c->rmax / b->R, cur, tiles, shapes, fut);
             }
+            if (b->shape >= 0)
+                for (size_t i = 0; i < tiles.size(); ++i) {
+                    const mrk::TileShape &t = mrk::kTileShapes[b->shape];
+                    shapes[i] = b->shape;
+                    tiles[i].ntx = (tiles[i].g.n[0] + t.tx - 1) / t.tx;
+                    tiles[i].nty = (tiles[i].g.n[1] + t.ty - 1) / t.ty;
+                }
             // a tile job's tile0 carries its tile shape until the jobs are
             // grouped by launch key; grouping then sets the real offsets
             for (size_t i = 0; i < tiles.size(); ++i) tiles[i].tile0 = shapes[i];
@@ -1373,6 +1403,8 @@ int mr_bind_workspace(mr_ctx *c, void *dev, size_t bytes)
             HIPCHK(c, hipMemcpyAsync(L.bcp_d, L.bcp.data(), L.bcp.size() * 4, hipMemcpyHostToDevice, c->st));
         if (!L.bel.empty())
             HIPCHK(c, hipMemcpyAsync(L.bel_d, L.bel.data(), L.bel.size() * 2, hipMemcpyHostToDevice, c->st));
+        if (!L.bpos.empty())
+            HIPCHK(c, hipMemcpyAsync(L.bpos_d, L.bpos.data(), L.bpos.size() * 2, hipMemcpyHostToDevice, c->st));
     }
     HIPCHK(c, hipMemcpyAsync(c->grids_d, devs.data(), devs.size() * sizeof(GridDev), hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
@@ -1829,6 +1861,14 @@ int mr_batch_macrostep(mr_batch *b, int nsteps)
         for (auto *c : b->ctx) advance_one(c);
         b->steps++;
     }
+    return MR_OK;
+}
+
+int mr_batch_set_tile_shape(mr_batch *b, int shape)
+{
+    if (!b || shape < -1 || shape >= mrk::NUM_TILE_SHAPES) return MR_ERR_ARG;
+    b->shape = shape;
+    b->built = false;
     return MR_OK;
 }
 

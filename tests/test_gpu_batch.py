@@ -75,3 +75,25 @@ def test_batch_rejects_unsupported(torch):
                       workloads.cylinder(nbg=96, ntheta=64, nr=32, half=6.0)])
     with pytest.raises(_lib.MrabError):
         Batch(mixed)
+
+
+def test_batch_common_tile_shape(torch):
+    """With one tile shape for the whole batch, every system still equals its
+    own macrosteps run with that shape."""
+    from paper_1805_06607_amd.batch import Batch
+    wls = workloads.batch_vortex(4, seed=7, smin=30, smax=60)
+    solo = _systems(wls)
+    for s in solo:
+        for g in range(s.ngrids):
+            s.set_tile_shape(g, 0)
+    grouped = _systems(workloads.batch_vortex(4, seed=7, smin=30, smax=60))
+    b = Batch(grouped)
+    b.set_tile_shape(0)
+    b.macrostep(9)
+    for s in solo:
+        s.macrostep(9)
+    torch.cuda.synchronize()
+    for a, c in zip(solo, grouped):
+        for x, y in zip(_snap(a), _snap(c)):
+            assert torch.equal(x, y)
+    b.close()
