@@ -465,6 +465,10 @@ struct TileCfg {
     static constexpr int MX = TX + 2 * HF, MY = TY + 2 * HF, MN = MX * MY;   // metric region
     static constexpr int FN = (TX + 2 * HF) * TY > TX * (TY + 2 * HF) ? (TX + 2 * HF) * TY : TX * (TY + 2 * HF);
     static constexpr int NIT = (PN + NT - 1) / NT;
+    // both directions' flux regions in one phase (one barrier less) when
+    // that takes at most two passes of the threads and the second flux
+    // buffer costs at most 16 KB of LDS
+    static constexpr bool BOTH = (TX + 2 * HF) * TY + TX * (TY + 2 * HF) <= 2 * NT && 4 * FN * 8 <= 16 * 1024;
 };
 
 // periodic wrap of a line index (the remainder is taken only off the line)
@@ -661,38 +665,61 @@ __device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph
     };
 
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
+    // flux region of direction m: (TX + 2HF) x TY for xi, TX x (TY + 2HF) for eta
+    constexpr int FN0 = (TX + 2 * HF) * TY, FN1 = TX * (TY + 2 * HF);
+    auto flux_region = [&](int m, int e, double *f) {
         const int FX = m == 0 ? TX + 2 * HF : TX;
-        const int FY = m == 0 ? TY : TY + 2 * HF;
         const int ox = m == 0 ? HF : 0, oy = m == 0 ? 0 : HF;
-        for (int e = tid; e < FX * FY; e += NT) {
-            int fx = e % FX, fy = e / FX;
-            int cx = HP - ox + fx, cy = HP - oy + fy;
-            double f[4] = {0.0, 0.0, 0.0, 0.0};
-            if ((sC[0][cy][cx] & 15) != CLS_HOLE) flux_at(m, cx, cy, f);
+        int fx = e % FX, fy = e / FX;
+        int cx = HP - ox + fx, cy = HP - oy + fy;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) sF[v][e] = f[v];
+        for (int v = 0; v < 4; ++v) f[v] = 0.0;
+        if ((sC[0][cy][cx] & 15) != CLS_HOLE) flux_at(m, cx, cy, f);
+    };
+    auto divergence = [&](int m, double (*S)[C::FN]) {
+        if (!inside) return;
+        const int FX = m == 0 ? TX + 2 * HF : TX;
+        int row = sC[m][cyo][cxo] & 15;
+        if (row == CLS_HOLE) return;
+        Vec<4> d = dsbp<SBP, 4>(row, [&](int o) {
+            int fx = m == 0 ? tx + HF + o : tx;
+            int fy = m == 0 ? ty : ty + HF + o;
+            int e = fy * FX + fx;
+            Vec<4> r;
+            r.v[0] = S[0][e]; r.v[1] = S[1][e]; r.v[2] = S[2][e]; r.v[3] = S[3][e];
+            return r;
+        });
+        double sc = CART ? g.inv_h[m] : 1.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] += sc * d.v[v];
+    };
+    if constexpr (C::BOTH) {
+        // enough threads for both flux regions at once: one phase, one barrier
+        __shared__ double sF1[4][C::FN];
+        for (int e = tid; e < FN0 + FN1; e += NT) {
+            const int m = e < FN0 ? 0 : 1, ee = m ? e - FN0 : e;
+            double f[4];
+            flux_region(m, ee, f);
+            double (*S)[C::FN] = m ? sF1 : sF;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) S[v][ee] = f[v];
         }
         __syncthreads();
-        if (inside) {
-            int row = sC[m][cyo][cxo] & 15;
-            if (row != CLS_HOLE) {
-                Vec<4> d = dsbp<SBP, 4>(row, [&](int o) {
-                    int fx = m == 0 ? tx + HF + o : tx;
-                    int fy = m == 0 ? ty : ty + HF + o;
-                    int e = fy * FX + fx;
-                    Vec<4> r;
-                    r.v[0] = sF[0][e]; r.v[1] = sF[1][e]; r.v[2] = sF[2][e]; r.v[3] = sF[3][e];
-                    return r;
-                });
-                double sc = CART ? g.inv_h[m] : 1.0;
+        divergence(0, sF);
+        divergence(1, sF1);
+    } else {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[v] += sc * d.v[v];
+        for (int m = 0; m < 2; ++m) {
+            for (int e = tid; e < (m ? FN1 : FN0); e += NT) {
+                double f[4];
+                flux_region(m, e, f);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sF[v][e] = f[v];
             }
+            __syncthreads();
+            divergence(m, sF);
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     // 3. epilogue
