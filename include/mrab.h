@@ -287,6 +287,52 @@ int mr_batch_set_tile_shape(mr_batch *batch, int shape);
 const char *mr_batch_last_error(const mr_batch *batch);
 void mr_batch_destroy(mr_batch *batch);
 
+/* Discrete adjoint (2D systems).  The derivative of a whole run -- the RK
+ * bootstrap of mr_mrab_start from initial states y0, then nmacro MRAB
+ * macrosteps at the context's macrostep H (held fixed: it is not
+ * differentiated) -- of
+ *     J = sum_i tau_i sum_k w_k p(q_grid(pts_k, t_i)),
+ * the time integral (trapezoid rule over the objective grid's own-step times
+ * from the start of the macrosteps, tau_i = its step, halved at both ends)
+ * of a weighted sum of the pressure p = (gamma - 1)(rho E - rho |u|^2 / 2)
+ * at listed points of one grid (a wall-pressure force when w_k = n_x ds).
+ * The run the adjoint differentiates is the library's own forward pass of
+ * the method: the right-hand sides, AB combinations and extrapolants are the
+ * kernels and rounding order of mr_mrab_macrostep; donor data take the
+ * two-launch path.  Every step of the derivative is a hand-written adjoint
+ * kernel (transposed SBP rows as gathers, exact local Jacobians of the
+ * pointwise flux, SAT and primitive maps by forward-mode dual numbers,
+ * donor data reversed per donor and stencil point from precomputed tables,
+ * so results do not depend on thread timing); macrosteps are reversed under
+ * a binomial checkpointing schedule with nsnap snapshots of every grid's
+ * state and history (slot 0 holds the start of the macrosteps).  The
+ * library allocates nothing: mr_adj_workspace_size reports the bytes the
+ * caller binds (states, histories, one macrostep's tape, the bootstrap
+ * states and the snapshots).  Errors: MR_ERR_ARG, MR_ERR_STATE (call order,
+ * no macrostep set), MR_ERR_UNSUPPORTED (3D grids).
+ *
+ * mr_adj_set_objective: host arrays, copied; points of `grid`, unique and
+ *     active; n = 0 removes the objective.
+ * mr_adj_rhs: lam_q = (d mr_rhs / d q)^T lamF for the coupled right-hand side
+ *     at states q (device, one array per grid, SoA nv x npts), donor data at
+ *     the same time included.
+ * mr_adj_forward: the forward pass alone: J and (yN non-null) the final
+ *     states.
+ * mr_adj_gradient: grad[g] = dL/dy0[g] for L = jscale * J + sum_g <lamN[g],
+ *     yN[g]> (lamN null or an entry null: zero); J, and in *nfwd the
+ *     macrosteps run forward (the first pass plus the recomputations).
+ *     nmacro <= 4096.
+ * mr_adj_schedule: host only; the forward macrosteps the reversal of nmacro
+ *     macrosteps recomputes with nsnap slots (slot 0 holding the start). */
+int mr_adj_set_objective(mr_ctx *ctx, int grid, int64_t n, const int64_t *pts, const double *w);
+int mr_adj_workspace_size(mr_ctx *ctx, int nsnap, size_t *bytes);
+int mr_adj_bind_workspace(mr_ctx *ctx, void *dev_ptr, size_t bytes);
+int mr_adj_rhs(mr_ctx *ctx, const double *const *dev_q, const double *const *dev_lamF, double *const *dev_lam_q);
+int mr_adj_forward(mr_ctx *ctx, int nmacro, const double *const *dev_y0, double *const *dev_yN, double *J);
+int mr_adj_gradient(mr_ctx *ctx, int nmacro, const double *const *dev_y0, const double *const *dev_lamN,
+                    double jscale, double *const *dev_grad, double *J, int64_t *nfwd);
+int mr_adj_schedule(int nmacro, int nsnap, int64_t *nfwd);
+
 const char *mr_last_error(const mr_ctx *ctx);
 void mr_destroy(mr_ctx *ctx);
 

@@ -99,7 +99,9 @@ class MRAB:
         self.t = t
 
     # ------------------------------------------------------------ macrostep
-    def macrostep(self):
+    def macrostep(self, observe=None):
+        """One macrostep; observe(g, y), when given, sees every level's state
+        right after each of its own steps."""
         G = len(self.y)
         for k in range(1, self.r_max + 1):
             per = [self.r_max // r for r in self.rates]
@@ -107,6 +109,8 @@ class MRAB:
             for g in range(G):
                 if ends[g]:
                     self.y[g] = combine(self.y[g], self.c_own[g], self.hist[g])
+                    if observe is not None:
+                        observe(g, self.y[g])
             states = []
             for g in range(G):
                 if ends[g]:

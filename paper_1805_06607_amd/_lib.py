@@ -75,6 +75,14 @@ SIGNATURES = {
     "mr_batch_set_tile_shape": [c_void_p, c_int],
     "mr_batch_last_error": [c_void_p],
     "mr_batch_destroy": [c_void_p],
+    "mr_adj_set_objective": [c_void_p, c_int, c_int64, POINTER(c_int64), POINTER(c_double)],
+    "mr_adj_workspace_size": [c_void_p, c_int, POINTER(c_size_t)],
+    "mr_adj_bind_workspace": [c_void_p, c_void_p, c_size_t],
+    "mr_adj_rhs": [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p)],
+    "mr_adj_forward": [c_void_p, c_int, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_double)],
+    "mr_adj_gradient": [c_void_p, c_int, POINTER(c_void_p), POINTER(c_void_p), c_double, POINTER(c_void_p),
+                        POINTER(c_double), POINTER(c_int64)],
+    "mr_adj_schedule": [c_int, c_int, POINTER(c_int64)],
     "mr_last_error": [c_void_p],
     "mr_destroy": [c_void_p],
 }

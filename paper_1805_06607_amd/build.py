@@ -30,7 +30,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(bdir, exist_ok=True)
     src = os.path.join(HERE, "csrc")
     objs = []
-    for name in ("kernels.hip",):
+    for name in ("kernels.hip", "adjoint.hip"):
         o = os.path.join(bdir, name + ".o")
         _run([HIPCC] + COMMON + DEVICE + ["-c", os.path.join(src, name), "-o", o], verbose)
         objs.append(o)

@@ -8,173 +8,11 @@
 // the first-derivative SBP operator (same Appendix), SAT interface penalty
 // eq. (int), AB combination eq. (ab_general), timestep eq. (ts_inv)-(ts_overall).
 #include "kern.h"
+#include "sbp_dev.h"
 
 #include <math.h>
 
 namespace mrk {
-
-template <int K>
-struct Vec {
-    double v[K];
-};
-
-// -------------------------------------------------------------- SBP rows
-// Diagonal-norm SBP 4-2 closure rows (left end); the right end mirrors them
-// with negated signs.  Interior: (1/12, -2/3, 0, 2/3, -1/12).
-// SBP 2-1: closure (-1, 1); interior (-1/2, 0, 1/2).
-#define C42_00 (-24.0 / 17.0)
-#define C42_01 (59.0 / 34.0)
-#define C42_02 (-4.0 / 17.0)
-#define C42_03 (-3.0 / 34.0)
-#define C42_20 (4.0 / 43.0)
-#define C42_21 (-59.0 / 86.0)
-#define C42_23 (59.0 / 86.0)
-#define C42_24 (-4.0 / 43.0)
-#define C42_30 (3.0 / 98.0)
-#define C42_32 (-59.0 / 98.0)
-#define C42_34 (32.0 / 49.0)
-#define C42_35 (-4.0 / 49.0)
-
-// First derivative (index spacing 1) of a K-vector field at a point whose
-// class row is `row`; f(o) returns the field at line offset o.
-template <int SBP, int K, class F>
-__device__ __forceinline__ Vec<K> dsbp(int row, F &&f)
-{
-    Vec<K> r;
-#pragma unroll
-    for (int k = 0; k < K; ++k) r.v[k] = 0.0;
-    auto add = [&](double c, int o) {
-        Vec<K> x = f(o);
-#pragma unroll
-        for (int k = 0; k < K; ++k) r.v[k] += c * x.v[k];
-    };
-    if (row == 0) {
-        if constexpr (SBP == 21) {
-            add(-0.5, -1); add(0.5, 1);
-        } else {
-            add(1.0 / 12.0, -2); add(-2.0 / 3.0, -1); add(2.0 / 3.0, 1); add(-1.0 / 12.0, 2);
-        }
-    } else if constexpr (SBP == 21) {
-        if (row == 1) { add(-1.0, 0); add(1.0, 1); }
-        else          { add(1.0, 0); add(-1.0, -1); }
-    } else {
-        switch (row) {
-        case 1: add(C42_00, 0); add(C42_01, 1); add(C42_02, 2); add(C42_03, 3); break;
-        case 2: add(-0.5, -1); add(0.5, 1); break;
-        case 3: add(C42_20, -2); add(C42_21, -1); add(C42_23, 1); add(C42_24, 2); break;
-        case 4: add(C42_30, -3); add(C42_32, -1); add(C42_34, 1); add(C42_35, 2); break;
-        case 5: add(-C42_00, 0); add(-C42_01, -1); add(-C42_02, -2); add(-C42_03, -3); break;
-        case 6: add(0.5, 1); add(-0.5, -1); break;
-        case 7: add(-C42_20, 2); add(-C42_21, 1); add(-C42_23, -1); add(-C42_24, -2); break;
-        default: add(-C42_30, 3); add(-C42_32, 1); add(-C42_34, -1); add(-C42_35, -2); break;
-        }
-    }
-    return r;
-}
-
-// neighbour along direction d at line offset o (periodic wrap)
-__device__ __forceinline__ int64_t nbr(const GridDev &g, int64_t p, const int *ic, int d, int o)
-{
-    int j = ic[d] + o;
-    if (g.periodic[d]) j = j < 0 ? j + g.n[d] : (j >= g.n[d] ? j - g.n[d] : j);
-    return p + (int64_t)(j - ic[d]) * g.stride[d];
-}
-
-__device__ __forceinline__ void coords(const GridDev &g, int64_t p, int *ic)
-{
-    ic[0] = (int)(p % g.n[0]);
-    int64_t r = p / g.n[0];
-    ic[1] = (int)(r % g.n[1]);
-    ic[2] = (int)(r / g.n[1]);
-}
-
-// primitives (u_1..u_D, T) of a conserved state
-template <int DIM>
-__device__ __forceinline__ Vec<DIM + 1> prim(const double *q, double gm1)
-{
-    Vec<DIM + 1> r;
-    double ri = 1.0 / q[0];
-    double ke = 0.0;
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) {
-        r.v[i] = q[1 + i] * ri;
-        ke += r.v[i] * q[1 + i];
-    }
-    double p = gm1 * (q[DIM + 1] - 0.5 * ke);
-    r.v[DIM] = p * ri;
-    return r;
-}
-
-template <int DIM>
-__device__ __forceinline__ void load_q(const double *q, int64_t N, int64_t p, double *out)
-{
-#pragma unroll
-    for (int v = 0; v < DIM + 2; ++v) out[v] = q[v * N + p];
-}
-
-// gradient d(phi_a)/dx_j of (u_1..u_D, T) at point p; qload(idx, out[nv])
-template <int DIM, int SBP, int CART, class QL>
-__device__ __forceinline__ void gradient(const GridDev &g, int64_t p, const int *ic, double gm1, QL &&qload,
-                                         double gr[DIM + 1][DIM])
-{
-    Vec<DIM + 1> dxi[DIM];
-#pragma unroll
-    for (int m = 0; m < DIM; ++m) {
-        int row = g.cls[m * g.npts + p] & 15;
-        dxi[m] = dsbp<SBP, DIM + 1>(row, [&](int o) {
-            double qq[DIM + 2];
-            qload(nbr(g, p, ic, m, o), qq);
-            return prim<DIM>(qq, gm1);
-        });
-    }
-    if constexpr (CART) {
-#pragma unroll
-        for (int a = 0; a <= DIM; ++a)
-#pragma unroll
-            for (int j = 0; j < DIM; ++j) gr[a][j] = g.inv_h[j] * dxi[j].v[a];
-    } else {
-        const int64_t N = g.npts;
-        double J = g.metric[(int64_t)(DIM * DIM) * N + p];
-        double M[DIM][DIM];
-#pragma unroll
-        for (int m = 0; m < DIM; ++m)
-#pragma unroll
-            for (int j = 0; j < DIM; ++j) M[m][j] = g.metric[(int64_t)(m * DIM + j) * N + p];
-#pragma unroll
-        for (int a = 0; a <= DIM; ++a)
-#pragma unroll
-            for (int j = 0; j < DIM; ++j) {
-                double s = 0.0;
-#pragma unroll
-                for (int m = 0; m < DIM; ++m) s += M[m][j] * dxi[m].v[a];
-                gr[a][j] = J * s;
-            }
-    }
-}
-
-// Cartesian viscous flux vectors (components 1..nv-1) at a point
-template <int DIM>
-__device__ __forceinline__ void viscous_flux(const Phys &ph, const double *u, double gr[DIM + 1][DIM],
-                                             double Fv[DIM][DIM + 1])
-{
-    double mre = ph.mu / ph.Re, lre = ph.lam / ph.Re;
-    double kc = ph.mu * ph.gamma / ((ph.gamma - 1.0) * ph.Re * ph.Pr);
-    double div = 0.0;
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) div += gr[i][i];
-#pragma unroll
-    for (int j = 0; j < DIM; ++j) {
-        double w = 0.0;
-#pragma unroll
-        for (int i = 0; i < DIM; ++i) {
-            double tau = mre * (gr[i][j] + gr[j][i]);
-            if (i == j) tau += lre * div;
-            Fv[j][i] = tau;
-            w += u[i] * tau;
-        }
-        Fv[j][DIM] = w + kc * gr[DIM][j];
-    }
-}
 
 // ------------------------------------------------------------ gradient pass
 template <int DIM, int SBP, int CART>
@@ -197,64 +35,6 @@ __global__ void __launch_bounds__(256) k_grad(GridDev g, double gm1, const doubl
     for (int a = 0; a <= DIM; ++a)
 #pragma unroll
         for (int j = 0; j < DIM; ++j) grad[(int64_t)(a * DIM + j) * N + p] = gr[a][j];
-}
-
-// --------------------------------------------------------- SAT (closed form)
-// K^{+-} dQ for the Euler flux Jacobian along the (non-normalised) direction
-// n, at state q, via characteristic wave strengths (entropy + shear waves at
-// U, acoustic waves at U +- c|n|); sgn = +1 for K+, -1 for K-.
-template <int DIM>
-__device__ __forceinline__ void k_apply(double gamma, const double *q, const double *n, int sgn, const double *dQ,
-                                        double *out)
-{
-    double rho = q[0], ri = 1.0 / rho;
-    double u[DIM], ke = 0.0;
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) { u[i] = q[1 + i] * ri; ke += u[i] * u[i]; }
-    double p = (gamma - 1.0) * (q[DIM + 1] - 0.5 * rho * ke);
-    double c2 = gamma * p * ri, c = sqrt(c2);
-    double H = (q[DIM + 1] + p) * ri;
-    double L2 = 0.0;
-#pragma unroll
-    for (int j = 0; j < DIM; ++j) L2 += n[j] * n[j];
-    double L = sqrt(L2), Li = 1.0 / L;
-    double nh[DIM], un = 0.0;
-#pragma unroll
-    for (int j = 0; j < DIM; ++j) { nh[j] = n[j] * Li; un += u[j] * nh[j]; }
-    double U = un * L;
-    // linearised primitive differences
-    double drho = dQ[0];
-    double du[DIM], udm = 0.0;
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) { du[i] = (dQ[1 + i] - u[i] * drho) * ri; udm += u[i] * dQ[1 + i]; }
-    double dp = (gamma - 1.0) * (dQ[DIM + 1] - udm + 0.5 * ke * drho);
-    double dun = 0.0;
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) dun += du[i] * nh[i];
-    double ae = drho - dp / c2;
-    double ap = (dp + rho * c * dun) / (2.0 * c2);
-    double am = (dp - rho * c * dun) / (2.0 * c2);
-    double l0 = U, lp = U + c * L, lm = U - c * L;
-    double w0 = 0.5 * (fabs(l0) + sgn * l0);
-    double wp = 0.5 * (fabs(lp) + sgn * lp);
-    double wm = 0.5 * (fabs(lm) + sgn * lm);
-    double a0 = w0 * ae, bp = wp * ap, bm = wm * am;
-    out[0] = a0 + bp + bm;
-    double us = 0.0;
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) {
-        double s = rho * (du[i] - dun * nh[i]);
-        us += u[i] * s;
-        out[1 + i] = a0 * u[i] + w0 * s + bp * (u[i] + c * nh[i]) + bm * (u[i] - c * nh[i]);
-    }
-    out[DIM + 1] = a0 * 0.5 * ke + w0 * us + bp * (H + c * un) + bm * (H - c * un);
-}
-
-__device__ __forceinline__ double add_nc(double acc, double c, double f)
-{
-#pragma clang fp contract(off)
-    double t = c * f;
-    return acc + t;
 }
 
 // --------------------------------------------- fused flux divergence + SAT + AB

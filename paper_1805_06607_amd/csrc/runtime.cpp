@@ -4,6 +4,7 @@
 // enqueued on the context's stream.
 #include "../../include/mrab.h"
 #include "kern.h"
+#include "adj.h"
 
 #include <algorithm>
 #include <array>
@@ -108,6 +109,8 @@ struct EvSet {
     std::vector<std::vector<hipEvent_t>> pool;     // per grid, Order::POOL each
 };
 
+struct AdjCtx;
+
 struct mr_ctx {
     mr_params P{};
     hipStream_t st = nullptr;
@@ -150,6 +153,7 @@ struct mr_ctx {
     Order ord;
     EvSet eager;
     std::vector<hipEvent_t> ev;
+    AdjCtx *adj = nullptr;                     // discrete adjoint (mr_adj_*)
 };
 
 // Many independent systems advanced together: per micro-time of the batch,
@@ -1183,6 +1187,769 @@ void advance_one(mr_ctx *c)
     c->nmacro++;
 }
 
+// ========================================================== discrete adjoint
+// Reverse-mode derivative of a whole run (RK bootstrap, then MRAB
+// macrosteps at the context's fixed macrostep H) of a wall-pressure
+// objective, with respect to the initial states.  The run is re-expressed as
+// a sequence of elementary operations on the integrator's quantities (own-step
+// AB combination, extrapolant, donor data, right-hand side, history push,
+// RK stage combinations); the reverse sweep applies their adjoints in the
+// opposite order.  The forward pass the adjoint differentiates is the one in
+// this section (same kernels and the same rounding order as the macrostep
+// calls for the AB combinations and right-hand sides; donor data by the
+// two-launch path).  Macrosteps are reversed under a binomial checkpointing
+// schedule (optimal split by dynamic programming over the number of free
+// snapshot slots); a snapshot holds every grid's state and history.
+
+}  // namespace
+
+struct AdjLink {
+    std::vector<int32_t> ustart, uent, cpts, cstart, cent, cself;
+    int32_t *ustart_d = nullptr, *uent_d = nullptr, *cpts_d = nullptr, *cstart_d = nullptr, *cent_d = nullptr,
+            *cself_d = nullptr;
+    double *uq = nullptr, *uk = nullptr;
+};
+
+struct AdjGrid {
+    double *lam_y = nullptr, *lam_ext = nullptr, *lys = nullptr;
+    double *lam_ring[mrk::MAXH] = {};
+    double *mu = nullptr, *kap = nullptr, *lqd = nullptr;
+    double *recv = nullptr, *lam_recv = nullptr;   // nslice slices of receiver rows
+    double *ys = nullptr;                          // rate + 1 states of one macrostep
+    double *ring[mrk::MAXH] = {};                  // forward history, oldest first
+    double *ext = nullptr;                         // rmax extrapolants (by micro-time)
+    double *snap = nullptr;                        // nsnap x (1 + m) states
+    double *boot = nullptr;                        // nboot + 1 bootstrap states
+    double *stg[4] = {}, *kk[4] = {}, *lk[4] = {}; // bootstrap stage states, derivatives, adjoints
+};
+
+struct AdjCtx {
+    bool tables = false, bound = false;
+    int nsnap = 0, nslice = 0, nboot = 0;
+    size_t bytes = 0;
+    char *ws = nullptr;
+    int og = -1;
+    std::vector<int32_t> opts;
+    std::vector<double> ow;
+    int32_t *opts_d = nullptr;
+    double *ow_d = nullptr, *acc = nullptr;
+    std::vector<AdjGrid> G;
+    std::vector<AdjLink> L;
+    std::vector<int> snap_pos;                     // macrostep held by each slot (-1 free)
+};
+
+namespace {
+
+// per link: the entries of each unique donor point, and the points the
+// donor gradients read with (unique point, direction, offset)
+void adj_tables(mr_ctx *c)
+{
+    AdjCtx &A = *c->adj;
+    if (A.tables) return;
+    A.L.assign(c->links.size(), {});
+    std::vector<int> off;
+    for (size_t li = 0; li < c->links.size(); ++li) {
+        const Link &L = c->links[li];
+        AdjLink &T = A.L[li];
+        const GridHost &D = c->G[L.dg];
+        const int S = c->S;
+        const size_t nu = L.upts.size();
+        T.ustart.assign(nu + 1, 0);
+        for (int64_t e = 0; e < L.n * S; ++e) T.ustart[c->euid[(size_t)L.first * S + e] + 1]++;
+        for (size_t u = 0; u < nu; ++u) T.ustart[u + 1] += T.ustart[u];
+        T.uent.assign((size_t)L.n * S, 0);
+        std::vector<int32_t> fill(T.ustart.begin(), T.ustart.end() - 1);
+        for (int64_t e = 0; e < L.n * S; ++e) T.uent[fill[c->euid[(size_t)L.first * S + e]]++] = (int32_t)e;
+        struct E { int32_t c, code; };
+        std::vector<E> es;
+        for (size_t u = 0; u < nu; ++u) {
+            int64_t p = L.upts[u];
+            int ic[3] = {(int)(p % D.n[0]), (int)((p / D.n[0]) % D.n[1]), (int)(p / ((int64_t)D.n[0] * D.n[1]))};
+            for (int m = 0; m < D.dim; ++m) {
+                row_offsets(c->P.sbp, D.cls[(size_t)m * D.npts + p] & 15, off);
+                for (int o : off) {
+                    int j = ic[m] + o;
+                    if (D.periodic[m]) j = ((j % D.n[m]) + D.n[m]) % D.n[m];
+                    int32_t q = (int32_t)(p + (int64_t)(j - ic[m]) * D.stride[m]);
+                    es.push_back({q, (int32_t)((u << 8) | (m << 4) | (o + 8))});
+                }
+            }
+            es.push_back({(int32_t)p, -1});   // the point itself
+        }
+        std::stable_sort(es.begin(), es.end(), [](const E &a, const E &b) { return a.c < b.c; });
+        T.cpts.clear();
+        T.cstart.assign(1, 0);
+        T.cent.clear();
+        T.cself.clear();
+        for (size_t i = 0; i < es.size();) {
+            size_t k = i;
+            int32_t self = -1;
+            while (k < es.size() && es[k].c == es[i].c) {
+                if (es[k].code < 0) {
+                    self = (int32_t)(std::lower_bound(L.upts.begin(), L.upts.end(), es[k].c) - L.upts.begin());
+                } else {
+                    T.cent.push_back(es[k].code);
+                }
+                ++k;
+            }
+            T.cpts.push_back(es[i].c);
+            T.cself.push_back(self);
+            T.cstart.push_back((int32_t)T.cent.size());
+            i = k;
+        }
+    }
+    A.tables = true;
+}
+
+size_t adj_layout(mr_ctx *c, char *base)
+{
+    AdjCtx &A = *c->adj;
+    Carver cv{base};
+    const int m = c->P.hist_len;
+    A.G.resize(c->G.size());
+    for (size_t gi = 0; gi < c->G.size(); ++gi) {
+        const GridHost &g = c->G[gi];
+        AdjGrid &a = A.G[gi];
+        const size_t ne = (size_t)(g.dim + 2) * g.npts, N = (size_t)g.npts;
+        auto st = [&]() { return cv.take<double>(ne); };
+        a.lam_y = st();
+        a.lam_ext = st();
+        a.lys = st();
+        for (int j = 0; j < m; ++j) a.lam_ring[j] = st();
+        a.mu = cv.take<double>((size_t)g.dim * (g.dim + 2) * N);
+        a.kap = cv.take<double>((size_t)g.dim * (g.dim + 1) * N);
+        a.lqd = st();
+        const size_t rows = g.recv_pts.size() * (size_t)((g.dim + 2) + g.dim * (g.dim + 1));
+        a.recv = rows ? cv.take<double>(rows * A.nslice) : nullptr;
+        a.lam_recv = rows ? cv.take<double>(rows * A.nslice) : nullptr;
+        a.ys = cv.take<double>(ne * (g.rate + 1));
+        for (int j = 0; j < m; ++j) a.ring[j] = st();
+        const bool donor_mid = c->rmax / g.rate > 1 && std::any_of(c->links.begin(), c->links.end(),
+                                                                  [&](const Link &L) { return L.dg == (int)gi; });
+        a.ext = donor_mid ? cv.take<double>(ne * c->rmax) : nullptr;
+        a.snap = cv.take<double>(ne * (1 + m) * A.nsnap);
+        a.boot = cv.take<double>(ne * (A.nboot + 1));
+        for (int k = 0; k < 4; ++k) {
+            a.stg[k] = st();
+            a.kk[k] = st();
+            a.lk[k] = st();
+        }
+    }
+    for (size_t li = 0; li < c->links.size(); ++li) {
+        AdjLink &T = A.L[li];
+        const int dim = c->G[c->links[li].dg].dim;
+        const size_t nu = c->links[li].upts.size();
+        T.ustart_d = cv.take<int32_t>(T.ustart.size());
+        T.uent_d = cv.take<int32_t>(T.uent.size() + 1);
+        T.cpts_d = cv.take<int32_t>(T.cpts.size() + 1);
+        T.cstart_d = cv.take<int32_t>(T.cstart.size());
+        T.cent_d = cv.take<int32_t>(T.cent.size() + 1);
+        T.cself_d = cv.take<int32_t>(T.cself.size() + 1);
+        T.uq = cv.take<double>(nu * (dim + 2) + 1);
+        T.uk = cv.take<double>(nu * dim * (dim + 1) + 1);
+    }
+    int64_t maxn = 1;
+    for (const GridHost &g : c->G) maxn = std::max(maxn, g.npts);
+    A.opts_d = cv.take<int32_t>((size_t)maxn);
+    A.ow_d = cv.take<double>((size_t)maxn);
+    A.acc = cv.take<double>(1);
+    return cv.off + ALIGN;
+}
+
+double *gstate(const AdjGrid &, const GridHost &g, double *base, int i)
+{
+    return base + (size_t)i * (g.dim + 2) * g.npts;
+}
+double *rslice(const mr_ctx *c, const GridHost &g, double *base, int s)
+{
+    if (!base) return nullptr;
+    return base + (size_t)s * g.recv_pts.size() * ((g.dim + 2) + g.dim * (g.dim + 1));
+}
+size_t rbytes(const GridHost &g) { return g.recv_pts.size() * ((g.dim + 2) + g.dim * (g.dim + 1)) * 8; }
+
+mrk::Objective adj_obj(const mr_ctx *c)
+{
+    mrk::Objective o{};
+    o.pts = c->adj->opts_d;
+    o.w = c->adj->ow_d;
+    o.n = (int)c->adj->opts.size();
+    o.gm1 = c->P.gamma - 1.0;
+    return o;
+}
+
+// donor data of link L from donor state Y into rows out (two-launch path)
+int adj_donor_fwd(mr_ctx *c, const Link &L, const double *Y, double *out)
+{
+    mrk::DonorLink a = link_base(c, L);
+    a.nj = 1;
+    a.ys[0] = Y;
+    a.out[0] = out;
+    HIPCHK(c, mrk::launch_donor(a, c->st));
+    return MR_OK;
+}
+
+// right-hand side of grid gi from q with receiver rows recv into F
+int adj_rhs_fwd(mr_ctx *c, int gi, const double *q, double *recv, double *F)
+{
+    GridHost &g = c->G[gi];
+    GridDev dev = g.dev;
+    dev.recv = recv;
+    mrk::Combine none{};
+    HIPCHK(c, mrk::launch_rhs_tile2d(dev, c->P.sbp, c->ph, q, F, none, shape_of(g), c->st));
+    return MR_OK;
+}
+
+// lam_q += (dR/dq)^T lamF and lam_recv = (dR/drecv)^T lamF for grid gi
+int adj_rhs_rev(mr_ctx *c, int gi, const double *q, double *recv, const double *lamF, double *lam_recv,
+                double *lam_q)
+{
+    GridHost &g = c->G[gi];
+    AdjGrid &a = c->adj->G[gi];
+    if (lam_recv) HIPCHK(c, hipMemsetAsync(lam_recv, 0, rbytes(g), c->st));
+    mrk::AdjRhs r{};
+    r.g = g.dev;
+    r.g.recv = recv;
+    r.ph = c->ph;
+    r.q = q;
+    r.lamF = lamF;
+    r.mu = a.mu;
+    r.kap = a.kap;
+    r.lqd = a.lqd;
+    r.lam_recv = lam_recv;
+    r.lam_q = lam_q;
+    HIPCHK(c, mrk::launch_adj_rhs(r, c->P.sbp, c->st));
+    return MR_OK;
+}
+
+// lam_Y += (d donor data / dY)^T lam_recv for link li
+int adj_donor_rev(mr_ctx *c, int li, const double *Y, const double *lam_recv, double *lam_Y)
+{
+    const Link &L = c->links[li];
+    AdjLink &T = c->adj->L[li];
+    mrk::AdjDonor d{};
+    d.g = c->G[L.dg].dev;
+    d.ph = c->ph;
+    d.y = Y;
+    d.lam_recv = lam_recv;
+    d.row0 = L.row0;
+    d.S = c->S;
+    d.upts = L.upts_d;
+    d.nu = (int64_t)L.upts.size();
+    d.ustart = T.ustart_d;
+    d.uent = T.uent_d;
+    d.w = c->ew_d + (size_t)L.first * c->S;
+    d.uq = T.uq;
+    d.uk = T.uk;
+    d.cpts = T.cpts_d;
+    d.nc = (int64_t)T.cpts.size();
+    d.cstart = T.cstart_d;
+    d.cent = T.cent_d;
+    d.cself = T.cself_d;
+    d.lam_y = lam_Y;
+    HIPCHK(c, mrk::launch_adj_donor(d, c->P.sbp, c->st));
+    return MR_OK;
+}
+
+// coupled right-hand side at one time: donor data from Y[dg] into slice s,
+// then every grid's right-hand side into K
+int adj_coupled_fwd(mr_ctx *c, const std::vector<double *> &Y, int s, const std::vector<double *> &K)
+{
+    AdjCtx &A = *c->adj;
+    for (const Link &L : c->links) {
+        int rc = adj_donor_fwd(c, L, Y[L.dg], rslice(c, c->G[L.rg], A.G[L.rg].recv, s));
+        if (rc) return rc;
+    }
+    for (size_t g = 0; g < c->G.size(); ++g) {
+        int rc = adj_rhs_fwd(c, (int)g, Y[g], rslice(c, c->G[g], A.G[g].recv, s), K[g]);
+        if (rc) return rc;
+    }
+    return MR_OK;
+}
+
+// lamY += (coupled right-hand side at Y, slice s)^T lamK
+int adj_coupled_rev(mr_ctx *c, const std::vector<double *> &Y, int s, const std::vector<double *> &lamK,
+                    const std::vector<double *> &lamY)
+{
+    AdjCtx &A = *c->adj;
+    for (size_t g = 0; g < c->G.size(); ++g) {
+        const GridHost &G = c->G[g];
+        int rc = adj_rhs_rev(c, (int)g, Y[g], rslice(c, G, A.G[g].recv, s), lamK[g],
+                             rslice(c, G, A.G[g].lam_recv, s), lamY[g]);
+        if (rc) return rc;
+    }
+    for (size_t li = 0; li < c->links.size(); ++li) {
+        const Link &L = c->links[li];
+        int rc = adj_donor_rev(c, (int)li, Y[L.dg], rslice(c, c->G[L.rg], A.G[L.rg].lam_recv, s), lamY[L.dg]);
+        if (rc) return rc;
+    }
+    return MR_OK;
+}
+
+int adj_axpy(mr_ctx *c, int64_t n, const double *src, std::initializer_list<double *> dst,
+             std::initializer_list<double> coef)
+{
+    std::vector<double *> d(dst);
+    std::vector<double> k(coef);
+    HIPCHK(c, mrk::launch_adj_axpy(n, src, (int)d.size(), d.data(), k.data(), c->st));
+    return MR_OK;
+}
+
+// objective weight of the objective grid's state after own step i (i = 0:
+// the start of the macrosteps) of a run of nmacro macrosteps: trapezoid rule
+double adj_tau(const mr_ctx *c, int i, int nmacro)
+{
+    const GridHost &g = c->G[c->adj->og];
+    const double hg = c->H / g.rate;
+    const int last = nmacro * g.rate;
+    return (i == 0 || i == last) ? 0.5 * hg : hg;
+}
+
+// bootstrap forward: boot[0] = y0, RK steps at h, history slots filled from
+// the first-stage derivatives; leaves the MRAB start state in ys[0] and the
+// history in ring[]
+int adj_boot_fwd(mr_ctx *c)
+{
+    AdjCtx &A = *c->adj;
+    const int G = (int)c->G.size(), m = c->P.hist_len;
+    const double d = c->h;
+    std::vector<double *> Y(G), K(G);
+    for (int n = 0; n <= A.nboot; ++n) {
+        for (int g = 0; g < G; ++g) {
+            Y[g] = gstate(A.G[g], c->G[g], A.G[g].boot, n);
+            K[g] = A.G[g].kk[0];
+        }
+        int rc = adj_coupled_fwd(c, Y, 0, K);
+        if (rc) return rc;
+        for (int g = 0; g < G; ++g) {
+            const GridHost &Gh = c->G[g];
+            const int per = c->rmax / Gh.rate, back = A.nboot - n;
+            if (back % per == 0 && back / per < m)
+                HIPCHK(c, hipMemcpyAsync(A.G[g].ring[m - 1 - back / per], A.G[g].kk[0], nelem(Gh) * 8,
+                                         hipMemcpyDeviceToDevice, c->st));
+        }
+        if (n == A.nboot) break;
+        auto stage_in = [&](int k) {
+            for (int g = 0; g < G; ++g) {
+                Y[g] = A.G[g].stg[k];
+                K[g] = A.G[g].kk[k];
+            }
+        };
+        for (int g = 0; g < G; ++g) {
+            const GridHost &Gh = c->G[g];
+            double *y = gstate(A.G[g], Gh, A.G[g].boot, n);
+            HIPCHK(c, mrk::launch_axpy(nelem(Gh), y, c->P.order <= 3 ? d / 3.0 : d / 2.0, A.G[g].kk[0],
+                                       A.G[g].stg[1], c->st));
+        }
+        stage_in(1);
+        if ((rc = adj_coupled_fwd(c, Y, 1, K))) return rc;
+        if (c->P.order <= 3) {
+            for (int g = 0; g < G; ++g) {
+                const GridHost &Gh = c->G[g];
+                double *y = gstate(A.G[g], Gh, A.G[g].boot, n);
+                HIPCHK(c, mrk::launch_axpy(nelem(Gh), y, 2.0 * d / 3.0, A.G[g].kk[1], A.G[g].stg[2], c->st));
+            }
+            stage_in(2);
+            if ((rc = adj_coupled_fwd(c, Y, 2, K))) return rc;
+            for (int g = 0; g < G; ++g) {
+                const GridHost &Gh = c->G[g];
+                double *y = gstate(A.G[g], Gh, A.G[g].boot, n);
+                HIPCHK(c, mrk::launch_rk3_final(nelem(Gh), y, d / 4.0, A.G[g].kk[0], A.G[g].kk[2],
+                                                gstate(A.G[g], Gh, A.G[g].boot, n + 1), c->st));
+            }
+        } else {
+            for (int g = 0; g < G; ++g) {
+                const GridHost &Gh = c->G[g];
+                double *y = gstate(A.G[g], Gh, A.G[g].boot, n);
+                HIPCHK(c, mrk::launch_axpy(nelem(Gh), y, d / 2.0, A.G[g].kk[1], A.G[g].stg[2], c->st));
+            }
+            stage_in(2);
+            if ((rc = adj_coupled_fwd(c, Y, 2, K))) return rc;
+            for (int g = 0; g < G; ++g) {
+                const GridHost &Gh = c->G[g];
+                double *y = gstate(A.G[g], Gh, A.G[g].boot, n);
+                HIPCHK(c, mrk::launch_axpy(nelem(Gh), y, d, A.G[g].kk[2], A.G[g].stg[3], c->st));
+            }
+            stage_in(3);
+            if ((rc = adj_coupled_fwd(c, Y, 3, K))) return rc;
+            for (int g = 0; g < G; ++g) {
+                const GridHost &Gh = c->G[g];
+                double *y = gstate(A.G[g], Gh, A.G[g].boot, n);
+                HIPCHK(c, mrk::launch_rk4_final(nelem(Gh), y, d / 6.0, A.G[g].kk[0], A.G[g].kk[1], A.G[g].kk[2],
+                                                A.G[g].kk[3], gstate(A.G[g], Gh, A.G[g].boot, n + 1), c->st));
+            }
+        }
+    }
+    for (int g = 0; g < G; ++g)
+        HIPCHK(c, hipMemcpyAsync(A.G[g].ys, gstate(A.G[g], c->G[g], A.G[g].boot, A.nboot), nelem(c->G[g]) * 8,
+                                 hipMemcpyDeviceToDevice, c->st));
+    return MR_OK;
+}
+
+// bootstrap reverse: on entry lam_y / lam_ring hold the adjoint of the MRAB
+// start state and history; on exit lam_y holds the adjoint of boot[0]
+int adj_boot_rev(mr_ctx *c)
+{
+    AdjCtx &A = *c->adj;
+    const int G = (int)c->G.size(), m = c->P.hist_len;
+    const double d = c->h;
+    std::vector<double *> Y(G), LK(G), LY(G), LS(G);
+    for (int g = 0; g < G; ++g) {
+        LY[g] = A.G[g].lam_y;
+        LS[g] = A.G[g].lys;
+    }
+    for (int n = A.nboot; n >= 0; --n) {
+        // recompute the stages of step n
+        for (int g = 0; g < G; ++g) Y[g] = gstate(A.G[g], c->G[g], A.G[g].boot, n);
+        if (n < A.nboot) {
+            // rerun step n's stages (fills stg[1..], kk[0..] and receiver slices 0..3)
+            std::vector<double *> K(G);
+            for (int g = 0; g < G; ++g) K[g] = A.G[g].kk[0];
+            int rc = adj_coupled_fwd(c, Y, 0, K);
+            if (rc) return rc;
+            const int ns = c->P.order <= 3 ? 3 : 4;
+            for (int s = 1; s < ns; ++s) {
+                double coef = c->P.order <= 3 ? (s == 1 ? d / 3.0 : 2.0 * d / 3.0) : (s == 3 ? d : d / 2.0);
+                for (int g = 0; g < G; ++g) {
+                    HIPCHK(c, mrk::launch_axpy(nelem(c->G[g]), Y[g], coef, A.G[g].kk[s - 1], A.G[g].stg[s], c->st));
+                }
+                std::vector<double *> Ys(G);
+                for (int g = 0; g < G; ++g) {
+                    Ys[g] = A.G[g].stg[s];
+                    K[g] = A.G[g].kk[s];
+                }
+                if ((rc = adj_coupled_fwd(c, Ys, s, K))) return rc;
+            }
+        } else {
+            std::vector<double *> K(G);
+            for (int g = 0; g < G; ++g) K[g] = A.G[g].kk[0];
+            int rc = adj_coupled_fwd(c, Y, 0, K);   // receiver rows of slice 0 at y_n
+            if (rc) return rc;
+        }
+        // first-stage adjoint: the history slot filled at n
+        for (int g = 0; g < G; ++g) {
+            const GridHost &Gh = c->G[g];
+            const int per = c->rmax / Gh.rate, back = A.nboot - n;
+            if (back % per == 0 && back / per < m)
+                HIPCHK(c, hipMemcpyAsync(A.G[g].lk[0], A.G[g].lam_ring[m - 1 - back / per], nelem(Gh) * 8,
+                                         hipMemcpyDeviceToDevice, c->st));
+            else
+                HIPCHK(c, hipMemsetAsync(A.G[g].lk[0], 0, nelem(Gh) * 8, c->st));
+            for (int k = 1; k < 4; ++k) HIPCHK(c, hipMemsetAsync(A.G[g].lk[k], 0, nelem(Gh) * 8, c->st));
+        }
+        if (n < A.nboot) {
+            auto stage_rev = [&](int s, double *const *to, std::initializer_list<double> coef) -> int {
+                // lys = f_s^T lk[s]; lam_y += lys; lk[to] += coef * lys
+                std::vector<double *> Ys(G);
+                for (int g = 0; g < G; ++g) {
+                    Ys[g] = A.G[g].stg[s];
+                    LK[g] = A.G[g].lk[s];
+                    HIPCHK(c, hipMemsetAsync(LS[g], 0, nelem(c->G[g]) * 8, c->st));
+                }
+                int rc = adj_coupled_rev(c, Ys, s, LK, LS);
+                if (rc) return rc;
+                for (int g = 0; g < G; ++g) {
+                    const double k = *coef.begin();
+                    rc = adj_axpy(c, nelem(c->G[g]), LS[g], {LY[g], to[g]}, {1.0, k});
+                    if (rc) return rc;
+                }
+                return MR_OK;
+            };
+            int rc;
+            std::vector<double *> to(G);
+            if (c->P.order <= 3) {
+                for (int g = 0; g < G; ++g)
+                    if ((rc = adj_axpy(c, nelem(c->G[g]), LY[g], {A.G[g].lk[0], A.G[g].lk[2]},
+                                       {d / 4.0, 3.0 * d / 4.0})))
+                        return rc;
+                for (int g = 0; g < G; ++g) to[g] = A.G[g].lk[1];
+                if ((rc = stage_rev(2, to.data(), {2.0 * d / 3.0}))) return rc;
+                for (int g = 0; g < G; ++g) to[g] = A.G[g].lk[0];
+                if ((rc = stage_rev(1, to.data(), {d / 3.0}))) return rc;
+            } else {
+                for (int g = 0; g < G; ++g)
+                    if ((rc = adj_axpy(c, nelem(c->G[g]), LY[g], {A.G[g].lk[0], A.G[g].lk[1], A.G[g].lk[2],
+                                                                  A.G[g].lk[3]},
+                                       {d / 6.0, d / 3.0, d / 3.0, d / 6.0})))
+                        return rc;
+                for (int g = 0; g < G; ++g) to[g] = A.G[g].lk[2];
+                if ((rc = stage_rev(3, to.data(), {d}))) return rc;
+                for (int g = 0; g < G; ++g) to[g] = A.G[g].lk[1];
+                if ((rc = stage_rev(2, to.data(), {d / 2.0}))) return rc;
+                for (int g = 0; g < G; ++g) to[g] = A.G[g].lk[0];
+                if ((rc = stage_rev(1, to.data(), {d / 2.0}))) return rc;
+            }
+        }
+        for (int g = 0; g < G; ++g) LK[g] = A.G[g].lk[0];
+        int rc = adj_coupled_rev(c, Y, 0, LK, LY);
+        if (rc) return rc;
+    }
+    return MR_OK;
+}
+
+// one MRAB macrostep (index n of nmacro) from ys[0] and ring[], leaving
+// every own-step state in ys[1..rate], the extrapolants in ext[k-1] and the
+// receiver rows in slice k-1; adds the objective terms when obj
+int adj_macro_fwd(mr_ctx *c, int n, int nmacro, bool obj)
+{
+    AdjCtx &A = *c->adj;
+    const int G = (int)c->G.size(), m = c->P.hist_len;
+    for (int k = 1; k <= c->rmax; ++k) {
+        bool ends[mrk::MAXG] = {};
+        for (int g = 0; g < G; ++g) ends[g] = k % (c->rmax / c->G[g].rate) == 0;
+        for (int g = 0; g < G; ++g) {
+            if (!ends[g]) continue;
+            const GridHost &Gh = c->G[g];
+            AdjGrid &a = A.G[g];
+            const int e = k / (c->rmax / Gh.rate);
+            mrk::Combine cb{};
+            cb.m = m;
+            for (int j = 0; j < m; ++j) {
+                cb.c[j] = c->c_own[g][j];
+                cb.hist[j] = a.ring[j];
+            }
+            cb.y_next = gstate(a, Gh, a.ys, e);
+            HIPCHK(c, mrk::launch_combine(nelem(Gh), gstate(a, Gh, a.ys, e - 1), cb, c->st));
+            if (obj && g == A.og)
+                HIPCHK(c, mrk::launch_obj(adj_obj(c), cb.y_next, Gh.npts, adj_tau(c, n * Gh.rate + e, nmacro), A.acc,
+                                          c->st));
+        }
+        bool made[mrk::MAXG] = {};
+        for (const Link &L : c->links) {
+            if (!ends[L.rg]) continue;
+            const GridHost &D = c->G[L.dg];
+            AdjGrid &a = A.G[L.dg];
+            const int per_d = c->rmax / D.rate, e = k / per_d, jp = k % per_d;
+            const double *Y = gstate(a, D, a.ys, e);
+            if (jp) {
+                double *X = gstate(a, D, a.ext, k - 1);
+                if (!made[L.dg]) {
+                    mrk::Combine cb{};
+                    cb.m = m;
+                    for (int j = 0; j < m; ++j) {
+                        cb.c[j] = c->beta[L.dg][jp][j];
+                        cb.hist[j] = a.ring[j];
+                    }
+                    cb.y_next = X;
+                    HIPCHK(c, mrk::launch_combine(nelem(D), Y, cb, c->st));
+                    made[L.dg] = true;
+                }
+                Y = X;
+            }
+            int rc = adj_donor_fwd(c, L, Y, rslice(c, c->G[L.rg], A.G[L.rg].recv, k - 1));
+            if (rc) return rc;
+        }
+        for (int g = 0; g < G; ++g) {
+            if (!ends[g]) continue;
+            const GridHost &Gh = c->G[g];
+            AdjGrid &a = A.G[g];
+            const int e = k / (c->rmax / Gh.rate);
+            int rc = adj_rhs_fwd(c, g, gstate(a, Gh, a.ys, e), rslice(c, Gh, a.recv, k - 1), a.ring[0]);
+            if (rc) return rc;
+            std::rotate(a.ring, a.ring + 1, a.ring + m);   // the new value is the newest
+        }
+    }
+    for (int g = 0; g < G; ++g) {
+        const GridHost &Gh = c->G[g];
+        AdjGrid &a = A.G[g];
+        HIPCHK(c, hipMemcpyAsync(a.ys, gstate(a, Gh, a.ys, Gh.rate), nelem(Gh) * 8, hipMemcpyDeviceToDevice, c->st));
+    }
+    return MR_OK;
+}
+
+// the reverse of macrostep n, right after adj_macro_fwd of the same
+// macrostep (ys[1..rate], ext[] and the receiver slices still hold its
+// quantities; the start state in ys[0] is not needed); lam_y / lam_ring:
+// adjoint of the end state and history in, of the start ones out
+int adj_macro_rev(mr_ctx *c, int n, int nmacro, double jscale)
+{
+    AdjCtx &A = *c->adj;
+    const int G = (int)c->G.size(), m = c->P.hist_len;
+    for (int k = c->rmax; k >= 1; --k) {
+        bool ends[mrk::MAXG] = {};
+        for (int g = 0; g < G; ++g) ends[g] = k % (c->rmax / c->G[g].rate) == 0;
+        for (int g = 0; g < G; ++g) {
+            if (!ends[g]) continue;
+            const GridHost &Gh = c->G[g];
+            AdjGrid &a = A.G[g];
+            const int e = k / (c->rmax / Gh.rate);
+            // undo the push: the newest slot's adjoint is the new value's
+            std::rotate(a.lam_ring, a.lam_ring + m - 1, a.lam_ring + m);
+            int rc = adj_rhs_rev(c, g, gstate(a, Gh, a.ys, e), rslice(c, Gh, a.recv, k - 1), a.lam_ring[0],
+                                 rslice(c, Gh, a.lam_recv, k - 1), a.lam_y);
+            if (rc) return rc;
+            HIPCHK(c, hipMemsetAsync(a.lam_ring[0], 0, nelem(Gh) * 8, c->st));
+            if (g == A.og && jscale != 0.0)
+                HIPCHK(c, mrk::launch_obj_adj(adj_obj(c), gstate(a, Gh, a.ys, e), Gh.npts,
+                                              jscale * adj_tau(c, n * Gh.rate + e, nmacro), a.lam_y, c->st));
+        }
+        for (int li = (int)c->links.size() - 1; li >= 0; --li) {
+            const Link &L = c->links[li];
+            if (!ends[L.rg]) continue;
+            const GridHost &D = c->G[L.dg];
+            AdjGrid &a = A.G[L.dg];
+            const int per_d = c->rmax / D.rate, e = k / per_d, jp = k % per_d;
+            const double *lr = rslice(c, c->G[L.rg], A.G[L.rg].lam_recv, k - 1);
+            int rc;
+            if (!jp) {
+                rc = adj_donor_rev(c, li, gstate(a, D, a.ys, e), lr, a.lam_y);
+                if (rc) return rc;
+                continue;
+            }
+            HIPCHK(c, hipMemsetAsync(a.lam_ext, 0, nelem(D) * 8, c->st));
+            rc = adj_donor_rev(c, li, gstate(a, D, a.ext, k - 1), lr, a.lam_ext);
+            if (rc) return rc;
+            std::vector<double *> dst(1, a.lam_y);
+            std::vector<double> coef(1, 1.0);
+            for (int j = 0; j < m; ++j) {
+                dst.push_back(a.lam_ring[j]);
+                coef.push_back(c->beta[L.dg][jp][j]);
+            }
+            HIPCHK(c, mrk::launch_adj_axpy(nelem(D), a.lam_ext, (int)dst.size(), dst.data(), coef.data(), c->st));
+        }
+        for (int g = 0; g < G; ++g) {
+            if (!ends[g]) continue;
+            AdjGrid &a = A.G[g];
+            std::vector<double> coef(c->c_own[g].begin(), c->c_own[g].end());
+            HIPCHK(c, mrk::launch_adj_axpy(nelem(c->G[g]), a.lam_y, m, a.lam_ring, coef.data(), c->st));
+        }
+    }
+    return MR_OK;
+}
+
+// snapshot slot s <- / -> the MRAB quantities (ys[0], ring)
+int adj_snap(mr_ctx *c, int s, bool store)
+{
+    AdjCtx &A = *c->adj;
+    const int m = c->P.hist_len;
+    for (size_t g = 0; g < c->G.size(); ++g) {
+        const GridHost &Gh = c->G[g];
+        AdjGrid &a = A.G[g];
+        const size_t nb = nelem(Gh) * 8;
+        double *base = gstate(a, Gh, a.snap, s * (1 + m));
+        for (int j = 0; j <= m; ++j) {
+            double *dev = j == 0 ? a.ys : a.ring[j - 1];
+            double *sn = base + (size_t)j * nelem(Gh);
+            HIPCHK(c, hipMemcpyAsync(store ? sn : dev, store ? dev : sn, nb, hipMemcpyDeviceToDevice, c->st));
+        }
+    }
+    return MR_OK;
+}
+
+// minimal forward macrosteps to reverse l macrosteps from a stored start
+// with s free snapshot slots, and the first split that attains it
+struct Sched {
+    std::vector<std::vector<int64_t>> cost;
+    std::vector<std::vector<int>> split;
+    void build(int L, int S)
+    {
+        cost.assign(L + 1, std::vector<int64_t>(S + 1, 0));
+        split.assign(L + 1, std::vector<int>(S + 1, 0));
+        for (int l = 1; l <= L; ++l)
+            for (int s = 0; s <= S; ++s) {
+                if (l == 1) {
+                    cost[l][s] = 1;
+                    continue;
+                }
+                if (s == 0) {
+                    cost[l][s] = (int64_t)l * (l + 1) / 2;
+                    continue;
+                }
+                int64_t best = INT64_MAX;
+                int bj = 1;
+                for (int j = 1; j < l; ++j) {
+                    int64_t v = j + cost[l - j][s - 1] + cost[j][s];
+                    if (v < best) {
+                        best = v;
+                        bj = j;
+                    }
+                }
+                cost[l][s] = best;
+                split[l][s] = bj;
+            }
+    }
+};
+
+// reverse macrosteps [a, b) of nmacro; the start of a is in slot sa; s free
+// slots beyond it
+int adj_reverse(mr_ctx *c, const Sched &S, int a, int b, int sa, int s, int nmacro, double jscale, int64_t &nfwd)
+{
+    AdjCtx &A = *c->adj;
+    if (b - a == 1) {
+        int rc = adj_snap(c, sa, false);
+        if (rc) return rc;
+        if ((rc = adj_macro_fwd(c, a, nmacro, false))) return rc;
+        nfwd++;
+        return adj_macro_rev(c, a, nmacro, jscale);
+    }
+    if (s == 0) {
+        for (int i = b - 1; i >= a; --i) {
+            int rc = adj_snap(c, sa, false);
+            if (rc) return rc;
+            for (int k = a; k < i; ++k) {
+                if ((rc = adj_macro_fwd(c, k, nmacro, false))) return rc;
+                nfwd++;
+            }
+            if ((rc = adj_macro_fwd(c, i, nmacro, false))) return rc;
+            nfwd++;
+            if ((rc = adj_macro_rev(c, i, nmacro, jscale))) return rc;
+        }
+        return MR_OK;
+    }
+    const int j = S.split[b - a][s];
+    int slot = -1;
+    for (int i = 0; i < A.nsnap; ++i)
+        if (A.snap_pos[i] < 0) {
+            slot = i;
+            break;
+        }
+    if (slot < 0) return fail(c, MR_ERR_STATE, "no free snapshot slot");
+    int rc = adj_snap(c, sa, false);
+    if (rc) return rc;
+    for (int k = a; k < a + j; ++k) {
+        if ((rc = adj_macro_fwd(c, k, nmacro, false))) return rc;
+        nfwd++;
+    }
+    if ((rc = adj_snap(c, slot, true))) return rc;
+    A.snap_pos[slot] = a + j;
+    if ((rc = adj_reverse(c, S, a + j, b, slot, s - 1, nmacro, jscale, nfwd))) return rc;
+    A.snap_pos[slot] = -1;
+    return adj_reverse(c, S, a, a + j, sa, s, nmacro, jscale, nfwd);
+}
+
+int adj_check(mr_ctx *c, int nmacro)
+{
+    if (!c->adj || !c->adj->bound) return fail(c, MR_ERR_STATE, "adjoint workspace not bound");
+    if (!c->have_dt) return fail(c, MR_ERR_STATE, "no macrostep set (mr_timestep or mr_set_macrostep)");
+    if (nmacro < 0) return fail(c, MR_ERR_ARG, "negative macrostep count");
+    return MR_OK;
+}
+
+// the whole forward run: bootstrap from y0, nmacro macrosteps; objective
+// accumulated into acc (zeroed first)
+int adj_run_fwd(mr_ctx *c, const double *const *y0, int nmacro, bool obj)
+{
+    AdjCtx &A = *c->adj;
+    for (size_t g = 0; g < c->G.size(); ++g)
+        HIPCHK(c, hipMemcpyAsync(A.G[g].boot, y0[g], nelem(c->G[g]) * 8, hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(c, hipMemsetAsync(A.acc, 0, 8, c->st));
+    int rc = adj_boot_fwd(c);
+    if (rc) return rc;
+    if (obj && A.og >= 0 && !A.opts.empty())
+        HIPCHK(c, mrk::launch_obj(adj_obj(c), A.G[A.og].ys, c->G[A.og].npts, adj_tau(c, 0, nmacro), A.acc, c->st));
+    for (int n = 0; n < nmacro; ++n)
+        if ((rc = adj_macro_fwd(c, n, nmacro, obj && A.og >= 0))) return rc;
+    return MR_OK;
+}
+
+int adj_upload_objective(mr_ctx *c)
+{
+    AdjCtx &A = *c->adj;
+    if (!A.bound || A.opts.empty()) return MR_OK;
+    HIPCHK(c, hipMemcpyAsync(A.opts_d, A.opts.data(), A.opts.size() * 4, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(A.ow_d, A.ow.data(), A.ow.size() * 8, hipMemcpyHostToDevice, c->st));
+    return MR_OK;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -1883,6 +2650,188 @@ void mr_batch_destroy(mr_batch *b)
 
 const char *mr_last_error(const mr_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
+// ------------------------------------------------------------ adjoint ABI
+int mr_adj_set_objective(mr_ctx *c, int grid, int64_t n, const int64_t *pts, const double *w)
+{
+    if (!c || n < 0 || (n > 0 && (!pts || !w))) return MR_ERR_ARG;
+    if (!c->finalized) return fail(c, MR_ERR_STATE, "mr_adj_set_objective before mr_finalize");
+    if (grid < 0 || grid >= (int)c->G.size()) return fail(c, MR_ERR_ARG, "bad grid id");
+    const GridHost &g = c->G[grid];
+    std::vector<int64_t> sorted(pts, pts + n);
+    std::sort(sorted.begin(), sorted.end());
+    for (int64_t i = 0; i < n; ++i) {
+        if (sorted[i] < 0 || sorted[i] >= g.npts) return fail(c, MR_ERR_ARG, "objective point out of range");
+        if (i && sorted[i] == sorted[i - 1]) return fail(c, MR_ERR_ARG, "objective point listed twice");
+        if (!g.iblank[sorted[i]]) return fail(c, MR_ERR_ARG, "objective point is blanked");
+        if (!std::isfinite(w[i])) return fail(c, MR_ERR_ARG, "non-finite objective weight");
+    }
+    if (!c->adj) c->adj = new AdjCtx();
+    AdjCtx &A = *c->adj;
+    A.og = n ? grid : -1;
+    A.opts.assign(pts, pts + n);
+    A.ow.assign(w, w + n);
+    return adj_upload_objective(c);
+}
+
+int mr_adj_workspace_size(mr_ctx *c, int nsnap, size_t *bytes)
+{
+    if (!c || !bytes || nsnap < 1) return MR_ERR_ARG;
+    if (!c->finalized) return fail(c, MR_ERR_STATE, "mr_adj_workspace_size before mr_finalize");
+    for (const GridHost &g : c->G)
+        if (g.dim != 2) return fail(c, MR_ERR_UNSUPPORTED, "the adjoint covers 2D systems");
+    if (!c->adj) c->adj = new AdjCtx();
+    AdjCtx &A = *c->adj;
+    if (A.bound) return fail(c, MR_ERR_STATE, "adjoint workspace already bound");
+    adj_tables(c);
+    A.nsnap = nsnap;
+    A.nslice = std::max(c->rmax, 4);
+    A.nboot = (c->P.hist_len - 1) * c->rmax;
+    A.bytes = adj_layout(c, nullptr);
+    *bytes = A.bytes;
+    return MR_OK;
+}
+
+int mr_adj_bind_workspace(mr_ctx *c, void *dev, size_t bytes)
+{
+    if (!c || !dev) return MR_ERR_ARG;
+    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_adj_bind_workspace before mr_bind_workspace");
+    if (!c->adj || !c->adj->bytes) return fail(c, MR_ERR_STATE, "mr_adj_bind_workspace before mr_adj_workspace_size");
+    AdjCtx &A = *c->adj;
+    if (A.bound) return fail(c, MR_ERR_STATE, "adjoint workspace already bound");
+    if (bytes < A.bytes) return fail(c, MR_ERR_ARG, "adjoint workspace too small (%zu < %zu)", bytes, A.bytes);
+    if ((uintptr_t)dev % ALIGN) return fail(c, MR_ERR_ARG, "adjoint workspace not 256-byte aligned");
+    A.ws = (char *)dev;
+    adj_layout(c, A.ws);
+    HIPCHK(c, hipMemsetAsync(A.ws, 0, A.bytes, c->st));
+    for (size_t li = 0; li < c->links.size(); ++li) {
+        AdjLink &T = A.L[li];
+        auto up = [&](int32_t *d, const std::vector<int32_t> &h) -> hipError_t {
+            return h.empty() ? hipSuccess : hipMemcpyAsync(d, h.data(), h.size() * 4, hipMemcpyHostToDevice, c->st);
+        };
+        HIPCHK(c, up(T.ustart_d, T.ustart));
+        HIPCHK(c, up(T.uent_d, T.uent));
+        HIPCHK(c, up(T.cpts_d, T.cpts));
+        HIPCHK(c, up(T.cstart_d, T.cstart));
+        HIPCHK(c, up(T.cent_d, T.cent));
+        HIPCHK(c, up(T.cself_d, T.cself));
+    }
+    A.snap_pos.assign(A.nsnap, -1);
+    A.bound = true;
+    int rc = adj_upload_objective(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    return MR_OK;
+}
+
+int mr_adj_rhs(mr_ctx *c, const double *const *q, const double *const *lamF, double *const *lam_q)
+{
+    if (!c || !q || !lamF || !lam_q) return MR_ERR_ARG;
+    if (!c->adj || !c->adj->bound) return fail(c, MR_ERR_STATE, "adjoint workspace not bound");
+    const int G = (int)c->G.size();
+    std::vector<double *> Y(G), K(G), LF(G), LQ(G);
+    for (int g = 0; g < G; ++g) {
+        if (!q[g] || !lamF[g] || !lam_q[g]) return fail(c, MR_ERR_ARG, "null pointer");
+        Y[g] = const_cast<double *>(q[g]);
+        K[g] = c->adj->G[g].kk[0];
+        LF[g] = const_cast<double *>(lamF[g]);
+        LQ[g] = lam_q[g];
+        HIPCHK(c, hipMemsetAsync(LQ[g], 0, nelem(c->G[g]) * 8, c->st));
+    }
+    int rc = adj_coupled_fwd(c, Y, 0, K);
+    if (rc) return rc;
+    return adj_coupled_rev(c, Y, 0, LF, LQ);
+}
+
+int mr_adj_forward(mr_ctx *c, int nmacro, const double *const *y0, double *const *yN, double *J)
+{
+    if (!c || !y0) return MR_ERR_ARG;
+    int rc = adj_check(c, nmacro);
+    if (rc) return rc;
+    for (size_t g = 0; g < c->G.size(); ++g)
+        if (!y0[g]) return fail(c, MR_ERR_ARG, "null initial state");
+    if ((rc = adj_run_fwd(c, y0, nmacro, true))) return rc;
+    AdjCtx &A = *c->adj;
+    if (yN)
+        for (size_t g = 0; g < c->G.size(); ++g)
+            if (yN[g])
+                HIPCHK(c, hipMemcpyAsync(yN[g], A.G[g].ys, nelem(c->G[g]) * 8, hipMemcpyDeviceToDevice, c->st));
+    double v = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&v, A.acc, 8, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (J) *J = v;
+    return MR_OK;
+}
+
+int mr_adj_gradient(mr_ctx *c, int nmacro, const double *const *y0, const double *const *lamN, double jscale,
+                    double *const *grad, double *J, int64_t *nfwd)
+{
+    if (!c || !y0 || !grad) return MR_ERR_ARG;
+    int rc = adj_check(c, nmacro);
+    if (rc) return rc;
+    if (nmacro > 4096) return fail(c, MR_ERR_ARG, "at most 4096 macrosteps per adjoint run");
+    AdjCtx &A = *c->adj;
+    const int G = (int)c->G.size(), m = c->P.hist_len;
+    for (int g = 0; g < G; ++g)
+        if (!y0[g] || !grad[g]) return fail(c, MR_ERR_ARG, "null initial state or gradient pointer");
+    // forward: bootstrap, the start in slot 0, every macrostep (objective)
+    for (int g = 0; g < G; ++g)
+        HIPCHK(c, hipMemcpyAsync(A.G[g].boot, y0[g], nelem(c->G[g]) * 8, hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(c, hipMemsetAsync(A.acc, 0, 8, c->st));
+    if ((rc = adj_boot_fwd(c))) return rc;
+    const bool obj = A.og >= 0;
+    if (obj)
+        HIPCHK(c, mrk::launch_obj(adj_obj(c), A.G[A.og].ys, c->G[A.og].npts, adj_tau(c, 0, nmacro), A.acc, c->st));
+    std::fill(A.snap_pos.begin(), A.snap_pos.end(), -1);
+    if ((rc = adj_snap(c, 0, true))) return rc;
+    A.snap_pos[0] = 0;
+    int64_t nf = 0;
+    for (int n = 0; n < nmacro; ++n) {
+        if ((rc = adj_macro_fwd(c, n, nmacro, obj))) return rc;
+        nf++;
+    }
+    // reverse: terminal adjoint, macrosteps under the checkpointing schedule,
+    // the start's objective term, the bootstrap
+    for (int g = 0; g < G; ++g) {
+        const size_t nb = nelem(c->G[g]) * 8;
+        if (lamN && lamN[g])
+            HIPCHK(c, hipMemcpyAsync(A.G[g].lam_y, lamN[g], nb, hipMemcpyDeviceToDevice, c->st));
+        else
+            HIPCHK(c, hipMemsetAsync(A.G[g].lam_y, 0, nb, c->st));
+        for (int j = 0; j < m; ++j) HIPCHK(c, hipMemsetAsync(A.G[g].lam_ring[j], 0, nb, c->st));
+    }
+    if (nmacro > 0) {
+        Sched S;
+        S.build(nmacro, A.nsnap - 1);
+        if ((rc = adj_reverse(c, S, 0, nmacro, 0, A.nsnap - 1, nmacro, jscale, nf))) return rc;
+    }
+    if ((rc = adj_snap(c, 0, false))) return rc;
+    if (obj && jscale != 0.0)
+        HIPCHK(c, mrk::launch_obj_adj(adj_obj(c), A.G[A.og].ys, c->G[A.og].npts, jscale * adj_tau(c, 0, nmacro),
+                                      A.G[A.og].lam_y, c->st));
+    if ((rc = adj_boot_rev(c))) return rc;
+    for (int g = 0; g < G; ++g)
+        HIPCHK(c, hipMemcpyAsync(grad[g], A.G[g].lam_y, nelem(c->G[g]) * 8, hipMemcpyDeviceToDevice, c->st));
+    double v = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&v, A.acc, 8, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (J) *J = v;
+    if (nfwd) *nfwd = nf;
+    return MR_OK;
+}
+
+int mr_adj_schedule(int nmacro, int nsnap, int64_t *nfwd)
+{
+    if (nmacro < 0 || nmacro > 4096 || nsnap < 1 || !nfwd) return MR_ERR_ARG;
+    if (nmacro == 0) {
+        *nfwd = 0;
+        return MR_OK;
+    }
+    Sched S;
+    S.build(nmacro, nsnap - 1);
+    *nfwd = S.cost[nmacro][nsnap - 1];
+    return MR_OK;
+}
+
 void mr_destroy(mr_ctx *c)
 {
     if (!c) return;
@@ -1893,6 +2842,7 @@ void mr_destroy(mr_ctx *c)
     free_evset(c->eager);
     for (auto s : c->gs)
         if (s) (void)hipStreamDestroy(s);
+    delete c->adj;
     delete c;
 }
 
