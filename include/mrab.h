@@ -248,7 +248,9 @@ int mr_get_tile_shape(const mr_ctx *ctx, int grid, int *shape, int *tx, int *ty,
 
 /* Autotuner (setup; synchronises): for every 2D grid, time reps launches of
  * each tile shape on the current state, writing only scratch buffers, and
- * keep the fastest.  Needs a bound workspace; leaves states, histories and
+ * keep the fastest.  The timed launches are queued behind a short wait on the
+ * device, so they run back to back and the host's launch rate does not enter
+ * the timing.  Needs a bound workspace; leaves states, histories and
  * the schedule untouched. */
 int mr_autotune(mr_ctx *ctx, int reps);
 

@@ -90,6 +90,7 @@ class Adjoint:
         self.s._check(self.lib.mr_adj_gradient(self.s.ctx, nmacro, _ptrs(ys), _ptrs(ln), jscale, _ptrs(grads),
                                                byref(J), byref(nf)), "mr_adj_gradient")
         self._alive = (ys, ln, grads)
+        self.last_nfwd = nf.value
         return J.value, grads, nf.value
 
 

@@ -161,6 +161,10 @@ hipError_t launch_rk4_final(int64_t n, const double *y, double a, const double *
 hipError_t launch_metrics2d(const GridDev &g, int sbp, const double *x, const double *y,
                             const double per[2][2], double *metric, hipStream_t st);
 hipError_t launch_dt(const GridDev &g, const Phys &ph, const double *q, double *dt, hipStream_t st);
+// occupy the stream for about `us` microseconds (at most 1 s) on one wave
+// of the device: launches queued behind it then run back to back, so a timing
+// of them measures the device, not the host's launch rate
+hipError_t launch_wait_us(double us, hipStream_t st);
 // block-partial reductions: mode 0 = min, 1 = max |x| (NaN/Inf -> +inf)
 hipError_t launch_reduce(int64_t n, const double *x, int mode, double *partial, int nblocks, hipStream_t st);
 

@@ -1332,6 +1332,26 @@ hipError_t launch_dt(const GridDev &g, const Phys &ph, const double *q, double *
     return hipGetLastError();
 }
 
+// one wave waits until the device's constant-rate clock has advanced by
+// `ticks` (bounded: it ends once the clock passes the mark)
+__global__ void k_wait_ticks(uint64_t ticks)
+{
+    const uint64_t t0 = wall_clock64();
+    while (wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(16);
+}
+
+hipError_t launch_wait_us(double us, hipStream_t st)
+{
+    int dev = 0, khz = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess) return e;
+    if (khz <= 0 || !(us >= 0.0) || us > 1e6) return hipErrorInvalidValue;
+    const uint64_t ticks = (uint64_t)(us * 1e-3 * khz);
+    hipLaunchKernelGGL(k_wait_ticks, dim3(1), dim3(64), 0, st, ticks);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce(int64_t n, const double *x, int mode, double *partial, int nblocks, hipStream_t st)
 {
     hipLaunchKernelGGL(k_reduce, dim3(nblocks), dim3(256), 0, st, n, x, mode, partial);

@@ -2505,7 +2505,10 @@ int mr_autotune(mr_ctx *c, int reps)
         double best = INFINITY;
         int pick = mrk::default_tile_shape(dev);
         for (int s = 0; s < mrk::NUM_TILE_SHAPES; ++s) {
+            // a warm-up launch, then a wait on the device long enough for the
+            // host to queue every timed launch behind it
             hipError_t e = mrk::launch_rhs_tile2d(dev, c->P.sbp, c->ph, g.y[g.cur], g.rk[0], cb, s, c->st);
+            if (e == hipSuccess) e = mrk::launch_wait_us(50.0 * reps + 200.0, c->st);
             if (e == hipSuccess) e = hipEventRecord(e0, c->st);
             for (int r = 0; r < reps && e == hipSuccess; ++r)
                 e = mrk::launch_rhs_tile2d(dev, c->P.sbp, c->ph, g.y[g.cur], g.rk[0], cb, s, c->st);
