@@ -191,6 +191,23 @@ int mr_mrab_resume(mr_ctx *ctx, double t);
 /* Current time and completed macrosteps. */
 int mr_time(const mr_ctx *ctx, double *t, int64_t *macrosteps);
 
+/* Checkpoint and restart of the integrator (every grid's state and its
+ * hist_len right-hand-side values, the time, the completed macrosteps and
+ * the macrostep H).  mr_save_bytes: the size of a checkpoint.  mr_save
+ * writes one into caller-owned device memory dev_buf (a 256-byte header,
+ * then per grid the state and the history values oldest first, each nv x
+ * npts) and synchronises the stream; mr_load reads one back into a context
+ * built from the same problem (same grids, hist_len), sets H, stages the next
+ * macrostep as mr_mrab_resume does (so it may follow mr_bind_workspace
+ * without mr_mrab_start), and synchronises.  Macrosteps after mr_load repeat
+ * those after mr_save bit for bit.  Errors: MR_ERR_ARG (null, buffer too
+ * small or misaligned), MR_ERR_STATE (save before mr_mrab_start or with a
+ * state set since; load before mr_bind_workspace), MR_ERR_SETUP (the
+ * checkpoint belongs to a different problem). */
+int mr_save_bytes(const mr_ctx *ctx, size_t *bytes);
+int mr_save(mr_ctx *ctx, void *dev_buf, size_t bytes);
+int mr_load(mr_ctx *ctx, const void *dev_buf, size_t bytes);
+
 /* AB coefficients (host, pure): alpha_j, j = 0..hist_len-1 oldest first, for
  * history nodes -(m-1)..0 in units of the step and target offset tau in (0,1]
  * (eq. vandermonde; minimum norm when hist_len > order, eq. ext_ab). */

@@ -75,6 +75,9 @@ SIGNATURES = {
     "mr_batch_set_tile_shape": [c_void_p, c_int],
     "mr_batch_last_error": [c_void_p],
     "mr_batch_destroy": [c_void_p],
+    "mr_save_bytes": [c_void_p, POINTER(c_size_t)],
+    "mr_save": [c_void_p, c_void_p, c_size_t],
+    "mr_load": [c_void_p, c_void_p, c_size_t],
     "mr_adj_set_objective": [c_void_p, c_int, c_int64, POINTER(c_int64), POINTER(c_double)],
     "mr_adj_workspace_size": [c_void_p, c_int, POINTER(c_size_t)],
     "mr_adj_bind_workspace": [c_void_p, c_void_p, c_size_t],

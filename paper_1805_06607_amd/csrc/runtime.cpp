@@ -2435,6 +2435,118 @@ int mr_kernel_time_grid(mr_ctx *c, int grid, double *total_ms, int *count)
 
 int mr_kernel_time(mr_ctx *c, double *total_ms, int *count) { return mr_kernel_time_grid(c, -1, total_ms, count); }
 
+}  // extern "C"
+
+namespace {
+// ---- checkpoints: 256-byte header, then per grid the state and the history
+// values oldest first
+struct SaveHeader {
+    char magic[8];
+    uint32_t version, ngrids;
+    int32_t hist_len, dim;
+    double t, H;
+    int64_t nmacro, npts_total;
+    uint64_t bytes;
+    char pad[256 - 64];
+};
+static_assert(sizeof(SaveHeader) == 256, "checkpoint header size");
+
+size_t save_bytes(const mr_ctx *c)
+{
+    size_t b = sizeof(SaveHeader);
+    for (const GridHost &g : c->G) b += (size_t)(1 + c->P.hist_len) * nelem(g) * 8;
+    return b;
+}
+
+int64_t npts_total(const mr_ctx *c)
+{
+    int64_t n = 0;
+    for (const GridHost &g : c->G) n += g.npts;
+    return n;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mr_save_bytes(const mr_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return MR_ERR_ARG;
+    *bytes = save_bytes(c);
+    return MR_OK;
+}
+
+int mr_save(mr_ctx *c, void *dev, size_t bytes)
+{
+    if (!c || !dev) return MR_ERR_ARG;
+    if (!c->started) return fail(c, MR_ERR_STATE, "mr_save before mr_mrab_start");
+    if (c->stale) return fail(c, MR_ERR_STATE, "state or history set since the last start/resume");
+    const size_t need = save_bytes(c);
+    if (bytes < need) return fail(c, MR_ERR_ARG, "checkpoint buffer too small (%zu < %zu)", bytes, need);
+    if ((uintptr_t)dev % 8) return fail(c, MR_ERR_ARG, "checkpoint buffer not 8-byte aligned");
+    SaveHeader h{};
+    std::memcpy(h.magic, "MRABSAVE", 8);
+    h.version = 1;
+    h.ngrids = (uint32_t)c->G.size();
+    h.hist_len = c->P.hist_len;
+    h.dim = c->P.dim;
+    h.t = c->t;
+    h.H = c->H;
+    h.nmacro = c->nmacro;
+    h.npts_total = npts_total(c);
+    h.bytes = need;
+    char *p = (char *)dev;
+    HIPCHK(c, hipMemcpyAsync(p, &h, sizeof h, hipMemcpyHostToDevice, c->st));
+    p += sizeof h;
+    for (const GridHost &g : c->G) {
+        const size_t nb = nelem(g) * 8;
+        HIPCHK(c, hipMemcpyAsync(p, g.y[g.cur], nb, hipMemcpyDeviceToDevice, c->st));
+        p += nb;
+        for (int j = 0; j < c->P.hist_len; ++j) {
+            HIPCHK(c, hipMemcpyAsync(p, slot(c, g, j), nb, hipMemcpyDeviceToDevice, c->st));
+            p += nb;
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    return MR_OK;
+}
+
+int mr_load(mr_ctx *c, const void *dev, size_t bytes)
+{
+    if (c) c->version++;
+    if (!c || !dev) return MR_ERR_ARG;
+    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_load before mr_bind_workspace");
+    if (bytes < sizeof(SaveHeader)) return fail(c, MR_ERR_ARG, "checkpoint buffer too small");
+    if ((uintptr_t)dev % 8) return fail(c, MR_ERR_ARG, "checkpoint buffer not 8-byte aligned");
+    SaveHeader h{};
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    HIPCHK(c, hipMemcpy(&h, dev, sizeof h, hipMemcpyDeviceToHost));
+    if (std::memcmp(h.magic, "MRABSAVE", 8) || h.version != 1) return fail(c, MR_ERR_SETUP, "not a checkpoint");
+    if (h.ngrids != c->G.size() || h.hist_len != c->P.hist_len || h.dim != c->P.dim ||
+        h.npts_total != npts_total(c) || h.bytes != save_bytes(c))
+        return fail(c, MR_ERR_SETUP, "checkpoint of a different problem");
+    if (bytes < h.bytes) return fail(c, MR_ERR_ARG, "checkpoint buffer shorter than its header states");
+    int rc = set_macrostep(c, h.H);
+    if (rc) return rc;
+    const char *p = (const char *)dev + sizeof h;
+    for (GridHost &g : c->G) {
+        const size_t nb = nelem(g) * 8;
+        HIPCHK(c, hipMemcpyAsync(g.y[g.cur], p, nb, hipMemcpyDeviceToDevice, c->st));
+        p += nb;
+        for (int j = 0; j < c->P.hist_len; ++j) {
+            HIPCHK(c, hipMemcpyAsync(slot(c, g, j), p, nb, hipMemcpyDeviceToDevice, c->st));
+            p += nb;
+        }
+    }
+    if ((rc = restage(c))) return rc;
+    c->t = h.t;
+    c->nmacro = h.nmacro;
+    c->started = true;
+    c->stale = false;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    return MR_OK;
+}
+
 int mr_set_option(mr_ctx *c, const char *name, int64_t value)
 {
     if (c) c->version++;

@@ -217,6 +217,21 @@ class System:
         """Launch-plan option ("rhs_two_pass")."""
         self._check(self.lib.mr_set_option(self.ctx, name.encode(), int(value)), "mr_set_option")
 
+    def save(self) -> torch.Tensor:
+        """Checkpoint of the integrator (states, histories, time, macrosteps,
+        H) in a new device tensor."""
+        n = c_size_t()
+        self._check(self.lib.mr_save_bytes(self.ctx, byref(n)), "mr_save_bytes")
+        buf = torch.empty(int(n.value), dtype=torch.uint8, device=self.device)
+        self._check(self.lib.mr_save(self.ctx, c_void_p(buf.data_ptr()), c_size_t(n.value)), "mr_save")
+        return buf
+
+    def load(self, buf: torch.Tensor) -> None:
+        """Restart from a checkpoint made by save() (this or another System
+        of the same problem)."""
+        b = buf.to(self.device).contiguous()
+        self._check(self.lib.mr_load(self.ctx, c_void_p(b.data_ptr()), c_size_t(b.numel())), "mr_load")
+
     def set_tile_shape(self, grid: int, shape: int):
         """Tile shape of a 2D grid's fused kernel (-1: size-based default)."""
         self._check(self.lib.mr_set_tile_shape(self.ctx, grid, shape), "mr_set_tile_shape")

@@ -61,7 +61,14 @@ def test_argument_validation_without_device():
     gid = ctypes.c_int()
     assert lib.mr_add_grid(ctx, ctypes.byref(d), ctypes.byref(gid)) == -3
     assert b"shorter than two closures" in lib.mr_last_error(ctx)
-    # call-order violation
+    # call-order violations
     out = ctypes.c_size_t()
     assert lib.mr_finalize(ctx, ctypes.byref(out)) == -2
+    assert lib.mr_save(ctx, ctypes.c_void_p(256), 1 << 20) == -2       # before mr_mrab_start
+    assert lib.mr_load(ctx, ctypes.c_void_p(256), 1 << 20) == -2       # before mr_bind_workspace
+    assert lib.mr_save(ctx, None, 0) == -1
+    assert lib.mr_adj_workspace_size(ctx, 4, ctypes.byref(out)) == -2  # before mr_finalize
+    assert lib.mr_adj_workspace_size(ctx, 0, ctypes.byref(out)) == -1
+    assert lib.mr_adj_bind_workspace(ctx, ctypes.c_void_p(256), 1 << 20) == -2
+    assert lib.mr_adj_gradient(ctx, 1, None, None, 1.0, None, None, None) == -1
     lib.mr_destroy(ctx)
