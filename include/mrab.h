@@ -245,6 +245,12 @@ int mr_kernel_time(mr_ctx *ctx, double *total_ms, int *count);
  *                        at its distinct donor points, the weighted sums);
  *                        0: always the values-then-gather launches, with a
  *                        separate extrapolation launch (default 1).
+ *  "rhs_tile3d"          3D grids: the gradient pass and the flux pass on LDS
+ *                        tiles of shape 0..3 (8x8x8, 16x8x4, 32x4x4, 16x4x4
+ *                        outputs; each thread evaluates its own point once,
+ *                        the halo slabs are evaluated per direction), or -1
+ *                        for the point-wise kernels (default 0).  Same
+ *                        formulas; results agree to rounding.
  *  "graph"               reserved: 1 (replaying captured HIP graphs of whole
  *                        macrostep periods) is switched off and returns
  *                        MR_ERR_UNSUPPORTED; 0 is accepted.

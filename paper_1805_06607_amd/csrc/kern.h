@@ -152,6 +152,14 @@ extern const TileShape kTileShapes[NUM_TILE_SHAPES];
 int default_tile_shape(const GridDev &g);
 hipError_t launch_rhs_tile2d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *F,
                              const Combine &cb, int shape, hipStream_t st);
+// 3D Cartesian right-hand side on LDS tiles of shape 0..NUM_TILE3D_SHAPES-1:
+// a gradient pass into grad (dim (dim+1) x npts scratch), then flux
+// divergence + SAT + AB update
+struct TileShape3 { int tx, ty, tz; };
+constexpr int NUM_TILE3D_SHAPES = 4;
+extern const TileShape3 kTile3dShapes[NUM_TILE3D_SHAPES];
+hipError_t launch_rhs_tile3d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *grad,
+                             double *F, const Combine &cb, int shape, hipStream_t st);
 hipError_t launch_combine(int64_t n, const double *y, const Combine &cb, hipStream_t st);
 hipError_t launch_axpy(int64_t n, const double *y, double a, const double *x, double *out, hipStream_t st);
 hipError_t launch_rk3_final(int64_t n, const double *y, double a, const double *k1, const double *k3,

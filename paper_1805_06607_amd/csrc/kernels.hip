@@ -38,176 +38,164 @@ __global__ void __launch_bounds__(256) k_grad(GridDev g, double gm1, const doubl
 }
 
 // --------------------------------------------- fused flux divergence + SAT + AB
-template <int DIM, int SBP, int CART>
-__global__ void __launch_bounds__(256) k_rhs(GridDev g, Phys ph, const double *__restrict__ q,
-                                             const double *__restrict__ grad, double *__restrict__ F,
-                                             Combine cb)
+// contravariant flux of direction m at point idx (Cartesian grids: the flux
+// vector of direction m), from the state and the stored gradients
+template <int DIM, int CART>
+__device__ __forceinline__ Vec<DIM + 2> fhat_at(const GridDev &g, const Phys &ph, const double *__restrict__ q,
+                                                const double *__restrict__ grad, int m, int64_t idx)
 {
     constexpr int NV = DIM + 2;
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= g.npts) return;
     const int64_t N = g.npts;
     const double gm1 = ph.gamma - 1.0;
-    int c0 = g.cls[p] & 15;
-    double r[NV];
-    if (c0 == CLS_HOLE) {
+    double qq[NV];
+    load_q<DIM>(q, N, idx, qq);
+    double ri = 1.0 / qq[0];
+    double u[DIM], ke = 0.0;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) r[v] = 0.0;
+    for (int i = 0; i < DIM; ++i) { u[i] = qq[1 + i] * ri; ke += u[i] * qq[1 + i]; }
+    double pr = gm1 * (qq[DIM + 1] - 0.5 * ke);
+    double gr[DIM + 1][DIM];
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) gr[a][j] = grad[(int64_t)(a * DIM + j) * N + idx];
+    double Fv[DIM][DIM + 1];
+    viscous_flux<DIM>(ph, u, gr, Fv);
+    Vec<NV> out;
+    if constexpr (CART) {
+        out.v[0] = qq[1 + m];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) out.v[1 + i] = qq[1 + i] * u[m] + (i == m ? pr : 0.0) - Fv[m][i];
+        out.v[NV - 1] = (qq[NV - 1] + pr) * u[m] - Fv[m][DIM];
     } else {
-        int ic[3];
-        coords(g, p, ic);
-        // contravariant flux of direction m at point idx
-        auto fhat = [&](int m, int64_t idx) {
-            double qq[NV];
-            load_q<DIM>(q, N, idx, qq);
-            double ri = 1.0 / qq[0];
-            double u[DIM], ke = 0.0;
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) { u[i] = qq[1 + i] * ri; ke += u[i] * qq[1 + i]; }
-            double pr = gm1 * (qq[DIM + 1] - 0.5 * ke);
-            double gr[DIM + 1][DIM];
+        for (int v = 0; v < NV; ++v) out.v[v] = 0.0;
 #pragma unroll
-            for (int a = 0; a <= DIM; ++a)
+        for (int j = 0; j < DIM; ++j) {
+            double Mmj = g.metric[(int64_t)(m * DIM + j) * N + idx];
+            out.v[0] += Mmj * qq[1 + j];
 #pragma unroll
-                for (int j = 0; j < DIM; ++j) gr[a][j] = grad[(int64_t)(a * DIM + j) * N + idx];
-            double Fv[DIM][DIM + 1];
-            viscous_flux<DIM>(ph, u, gr, Fv);
-            Vec<NV> out;
-            if constexpr (CART) {
-                out.v[0] = qq[1 + m];
-#pragma unroll
-                for (int i = 0; i < DIM; ++i) out.v[1 + i] = qq[1 + i] * u[m] + (i == m ? pr : 0.0) - Fv[m][i];
-                out.v[NV - 1] = (qq[NV - 1] + pr) * u[m] - Fv[m][DIM];
-            } else {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) out.v[v] = 0.0;
-#pragma unroll
-                for (int j = 0; j < DIM; ++j) {
-                    double Mmj = g.metric[(int64_t)(m * DIM + j) * N + idx];
-                    out.v[0] += Mmj * qq[1 + j];
-#pragma unroll
-                    for (int i = 0; i < DIM; ++i)
-                        out.v[1 + i] += Mmj * (qq[1 + i] * u[j] + (i == j ? pr : 0.0) - Fv[j][i]);
-                    out.v[NV - 1] += Mmj * ((qq[NV - 1] + pr) * u[j] - Fv[j][DIM]);
-                }
-            }
-            return out;
-        };
-        double acc[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-#pragma unroll
-        for (int m = 0; m < DIM; ++m) {
-            int row = g.cls[m * N + p] & 15;
-            Vec<NV> d = dsbp<SBP, NV>(row, [&](int o) { return fhat(m, nbr(g, p, ic, m, o)); });
-            double sc = CART ? g.inv_h[m] : 1.0;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) acc[v] += sc * d.v[v];
+            for (int i = 0; i < DIM; ++i)
+                out.v[1 + i] += Mmj * (qq[1 + i] * u[j] + (i == j ? pr : 0.0) - Fv[j][i]);
+            out.v[NV - 1] += Mmj * ((qq[NV - 1] + pr) * u[j] - Fv[j][DIM]);
         }
-        double J = CART ? 1.0 : g.metric[(int64_t)(DIM * DIM) * N + p];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) r[v] = -J * acc[v];
+    }
+    return out;
+}
 
-        // SAT penalties at run ends (directions ascending, run start first)
-        bool any = false;
+// SAT penalties of point p added into r: at run ends, directions ascending
+template <int DIM, int CART>
+__device__ __forceinline__ void sat_point(const GridDev &g, const Phys &ph, const double *__restrict__ q,
+                                          const double *__restrict__ grad, int64_t p, double *r)
+{
+    constexpr int NV = DIM + 2;
+    const int64_t N = g.npts;
+    // SAT penalties at run ends (directions ascending, run start first)
+    bool any = false;
 #pragma unroll
+    for (int m = 0; m < DIM; ++m) {
+        int c = g.cls[m * N + p];
+        any |= ((c >> 4) & 3) != 0;
+    }
+    if (any) {
+        double qp[NV];
+        load_q<DIM>(q, N, p, qp);
+        double u[DIM];
+        double ri = 1.0 / qp[0];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) u[i] = qp[1 + i] * ri;
+        double gr[DIM + 1][DIM];
+#pragma unroll
+        for (int a = 0; a <= DIM; ++a)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) gr[a][j] = grad[(int64_t)(a * DIM + j) * N + p];
+        double Fv[DIM][DIM + 1];
+        viscous_flux<DIM>(ph, u, gr, Fv);
         for (int m = 0; m < DIM; ++m) {
             int c = g.cls[m * N + p];
-            any |= ((c >> 4) & 3) != 0;
-        }
-        if (any) {
-            double qp[NV];
-            load_q<DIM>(q, N, p, qp);
-            double u[DIM];
-            double ri = 1.0 / qp[0];
+            int bc = (c >> 4) & 3;
+            if (!bc) continue;
+            int row = c & 15;
+            int sgn = (row == 1) ? 1 : -1;
+            double kap[DIM], k2 = 0.0;
+            if constexpr (CART) {
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) u[i] = qp[1 + i] * ri;
-            double gr[DIM + 1][DIM];
+                for (int j = 0; j < DIM; ++j) kap[j] = (j == m) ? g.inv_h[m] : 0.0;
+            } else {
+                double Jp = g.metric[(int64_t)(DIM * DIM) * N + p];
 #pragma unroll
-            for (int a = 0; a <= DIM; ++a)
+                for (int j = 0; j < DIM; ++j) kap[j] = Jp * g.metric[(int64_t)(m * DIM + j) * N + p];
+            }
 #pragma unroll
-                for (int j = 0; j < DIM; ++j) gr[a][j] = grad[(int64_t)(a * DIM + j) * N + p];
-            double Fv[DIM][DIM + 1];
-            viscous_flux<DIM>(ph, u, gr, Fv);
-            for (int m = 0; m < DIM; ++m) {
-                int c = g.cls[m * N + p];
-                int bc = (c >> 4) & 3;
-                if (!bc) continue;
-                int row = c & 15;
-                int sgn = (row == 1) ? 1 : -1;
-                double kap[DIM], k2 = 0.0;
-                if constexpr (CART) {
+            for (int j = 0; j < DIM; ++j) k2 += kap[j] * kap[j];
+            double dQ[NV], dV[NV], s2[NV];
+            double sigI, sig1 = ph.mu * k2 / (2.0 * ph.Re);
+            bool use_s2 = true;
 #pragma unroll
-                    for (int j = 0; j < DIM; ++j) kap[j] = (j == m) ? g.inv_h[m] : 0.0;
-                } else {
-                    double Jp = g.metric[(int64_t)(DIM * DIM) * N + p];
+            for (int v = 0; v < NV; ++v) s2[v] = 0.0;
+            // own viscous flux along kappa (components 1..nv-1)
 #pragma unroll
-                    for (int j = 0; j < DIM; ++j) kap[j] = Jp * g.metric[(int64_t)(m * DIM + j) * N + p];
-                }
+            for (int v = 1; v < NV; ++v) {
+                double s = 0.0;
 #pragma unroll
-                for (int j = 0; j < DIM; ++j) k2 += kap[j] * kap[j];
-                double dQ[NV], dV[NV], s2[NV];
-                double sigI, sig1 = ph.mu * k2 / (2.0 * ph.Re);
-                bool use_s2 = true;
+                for (int j = 0; j < DIM; ++j) s += kap[j] * Fv[j][v - 1];
+                s2[v] = s;
+            }
+            if (bc == 1) {
+                const double *rb = g.recv + (int64_t)g.recv_idx[p] * (NV + DIM * (NV - 1));
 #pragma unroll
-                for (int v = 0; v < NV; ++v) s2[v] = 0.0;
-                // own viscous flux along kappa (components 1..nv-1)
+                for (int v = 0; v < NV; ++v) { dQ[v] = qp[v] - rb[v]; dV[v] = dQ[v]; }
 #pragma unroll
                 for (int v = 1; v < NV; ++v) {
                     double s = 0.0;
 #pragma unroll
-                    for (int j = 0; j < DIM; ++j) s += kap[j] * Fv[j][v - 1];
-                    s2[v] = s;
+                    for (int j = 0; j < DIM; ++j) s += kap[j] * rb[NV + j * (NV - 1) + (v - 1)];
+                    s2[v] -= s;
                 }
-                if (bc == 1) {
-                    const double *rb = g.recv + (int64_t)g.recv_idx[p] * (NV + DIM * (NV - 1));
+                sigI = ph.sig_iface;
+            } else if (bc == 2) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) { dQ[v] = qp[v] - rb[v]; dV[v] = dQ[v]; }
+                for (int v = 0; v < NV; ++v) { dQ[v] = qp[v] - ph.q_inf[v]; dV[v] = dQ[v]; }
+                sigI = ph.sig_bc;
+            } else {
+                // wall: reflected normal momentum (inviscid), rest at T_wall (viscous)
+                double kn = sqrt(k2), mn = 0.0;
 #pragma unroll
-                    for (int v = 1; v < NV; ++v) {
-                        double s = 0.0;
+                for (int i = 0; i < DIM; ++i) mn += qp[1 + i] * kap[i];
+                mn /= kn;
+                dQ[0] = 0.0;
+                dV[0] = 0.0;
 #pragma unroll
-                        for (int j = 0; j < DIM; ++j) s += kap[j] * rb[NV + j * (NV - 1) + (v - 1)];
-                        s2[v] -= s;
-                    }
-                    sigI = ph.sig_iface;
-                } else if (bc == 2) {
+                for (int i = 0; i < DIM; ++i) { dQ[1 + i] = 2.0 * mn * kap[i] / kn; dV[1 + i] = qp[1 + i]; }
+                dQ[NV - 1] = 0.0;
+                dV[NV - 1] = qp[NV - 1] - qp[0] * ph.T_wall / (ph.gamma - 1.0);
+                sigI = ph.sig_bc;
+                sig1 = ph.wall_visc * ph.mu * k2 / ph.Re;
+                use_s2 = false;
+            }
+            double KdQ[NV];
+            k_apply<DIM>(ph.gamma, qp, kap, sgn, dQ, KdQ);
+            double hs = 0.5 * sgn;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) { dQ[v] = qp[v] - ph.q_inf[v]; dV[v] = dQ[v]; }
-                    sigI = ph.sig_bc;
-                } else {
-                    // wall: reflected normal momentum (inviscid), rest at T_wall (viscous)
-                    double kn = sqrt(k2), mn = 0.0;
-#pragma unroll
-                    for (int i = 0; i < DIM; ++i) mn += qp[1 + i] * kap[i];
-                    mn /= kn;
-                    dQ[0] = 0.0;
-                    dV[0] = 0.0;
-#pragma unroll
-                    for (int i = 0; i < DIM; ++i) { dQ[1 + i] = 2.0 * mn * kap[i] / kn; dV[1 + i] = qp[1 + i]; }
-                    dQ[NV - 1] = 0.0;
-                    dV[NV - 1] = qp[NV - 1] - qp[0] * ph.T_wall / (ph.gamma - 1.0);
-                    sigI = ph.sig_bc;
-                    sig1 = ph.wall_visc * ph.mu * k2 / ph.Re;
-                    use_s2 = false;
-                }
-                double KdQ[NV];
-                k_apply<DIM>(ph.gamma, qp, kap, sgn, dQ, KdQ);
-                double hs = 0.5 * sgn;
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    double pen = -(sigI * KdQ[v] + sig1 * dV[v]) * ph.p0inv;
-                    if (use_s2) pen += hs * s2[v] * ph.p0inv;
-                    r[v] += pen;
-                }
+            for (int v = 0; v < NV; ++v) {
+                double pen = -(sigI * KdQ[v] + sig1 * dV[v]) * ph.p0inv;
+                if (use_s2) pen += hs * s2[v] * ph.p0inv;
+                r[v] += pen;
             }
         }
     }
+}
+
+// store F at p and, when fused, y_next = y + sum_j c_j F_j, oldest first, the
+// new F last; each product and sum rounded separately
+template <int DIM>
+__device__ __forceinline__ void store_step(const double *__restrict__ q, double *__restrict__ F, const Combine &cb,
+                                           int64_t N, int64_t p, const double *r)
+{
+    constexpr int NV = DIM + 2;
 #pragma unroll
     for (int v = 0; v < NV; ++v) F[v * N + p] = r[v];
     if (cb.m > 0) {
-        // y_next = y + sum_j c_j F_j, oldest first, the new F last; each
-        // product and sum rounded separately
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             int64_t e = v * N + p;
@@ -219,6 +207,278 @@ __global__ void __launch_bounds__(256) k_rhs(GridDev g, Phys ph, const double *_
             cb.y_next[e] = acc;
         }
     }
+}
+
+template <int DIM, int SBP, int CART>
+__global__ void __launch_bounds__(256) k_rhs(GridDev g, Phys ph, const double *__restrict__ q,
+                                             const double *__restrict__ grad, double *__restrict__ F,
+                                             Combine cb)
+{
+    constexpr int NV = DIM + 2;
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= g.npts) return;
+    const int64_t N = g.npts;
+    int c0 = g.cls[p] & 15;
+    double r[NV];
+    if (c0 == CLS_HOLE) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) r[v] = 0.0;
+    } else {
+        int ic[3];
+        coords(g, p, ic);
+        double acc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+            int row = g.cls[m * N + p] & 15;
+            Vec<NV> d = dsbp<SBP, NV>(row, [&](int o) { return fhat_at<DIM, CART>(g, ph, q, grad, m, nbr(g, p, ic, m, o)); });
+            double sc = CART ? g.inv_h[m] : 1.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] += sc * d.v[v];
+        }
+        double J = CART ? 1.0 : g.metric[(int64_t)(DIM * DIM) * N + p];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) r[v] = -J * acc[v];
+        sat_point<DIM, CART>(g, ph, q, grad, p, r);
+    }
+    store_step<DIM>(q, F, cb, N, p, r);
+}
+
+// 3D tiles of TX x TY x TZ outputs, one thread per output.  For each
+// direction m, a quantity needed on the tile plus R points along m (R: the
+// reach of a first-derivative row) is staged in LDS: the tile's own values
+// come from registers (each thread evaluates its own point once, for every
+// direction), only the 2R slabs of halo points are evaluated per direction.
+// Periodic directions wrap; points off the grid or in holes stage zeros (no
+// row of an active output reads them).
+template <int TX, int TY, int TZ, int R>
+struct Tile3 {
+    static constexpr int NT = TX * TY * TZ;
+    static constexpr int R0 = (TX + 2 * R) * TY * TZ, R1 = TX * (TY + 2 * R) * TZ, R2 = TX * TY * (TZ + 2 * R);
+    static constexpr int RMAX = R0 > R1 ? (R0 > R2 ? R0 : R2) : (R1 > R2 ? R1 : R2);
+    __device__ static constexpr int T(int m) { return m == 0 ? TX : (m == 1 ? TY : TZ); }
+    // region extents of direction m
+    __device__ static void ext(int m, int *e)
+    {
+        e[0] = TX + (m == 0 ? 2 * R : 0);
+        e[1] = TY + (m == 1 ? 2 * R : 0);
+        e[2] = TZ + (m == 2 ? 2 * R : 0);
+    }
+    // halo slab entry h of direction m -> region coordinates
+    __device__ static void halo(int m, int h, int *c)
+    {
+        const int o1 = m == 0 ? 1 : 0, o2 = m == 2 ? 1 : 2;   // the other two directions, ascending
+        const int n1 = T(o1);
+        const int s = h % (2 * R), r = h / (2 * R);
+        c[m] = s < R ? s : s + T(m);
+        c[o1] = r % n1;
+        c[o2] = r / n1;
+    }
+    // global index of region coordinates c of direction m (false: off the grid)
+    __device__ static bool global(const GridDev &g, const int *t0, int m, const int *c, int64_t &idx)
+    {
+        idx = 0;
+        bool ok = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int j = t0[d] + c[d] - (d == m ? R : 0);
+            if (d == m && g.periodic[d]) j = j < 0 ? j + g.n[d] : (j >= g.n[d] ? j - g.n[d] : j);
+            ok = ok && j >= 0 && j < g.n[d];
+            idx += (int64_t)j * g.stride[d];
+        }
+        return ok;
+    }
+};
+
+// the three directional flux vectors of a Cartesian 3D point from one load of
+// its state and gradients (the formulas of fhat_at)
+__device__ __forceinline__ void fluxes3(const GridDev &g, const Phys &ph, const double *__restrict__ q,
+                                        const double *__restrict__ grad, int64_t idx, Vec<5> *out)
+{
+#pragma unroll
+    for (int m = 0; m < 3; ++m) out[m] = fhat_at<3, 1>(g, ph, q, grad, m, idx);
+}
+
+// 3D Cartesian gradient pass on tiles: grad[(a*3+j)*N + p] = d(u, v, w, T)_a / dx_j
+// (zero at holes), the formulas of k_grad
+template <int SBP, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(TX * TY * TZ) k_grad_tile3d(GridDev g, double gm1, const double *__restrict__ q,
+                                                              double *__restrict__ grad, int ntx, int nty, int ntz)
+{
+    constexpr int R = SBP == 21 ? 1 : 3;
+    using C = Tile3<TX, TY, TZ, R>;
+    __shared__ double sW[4][C::RMAX];
+    const int tile = xcd_tile(blockIdx.x, ntx * nty * ntz);
+    const int t0[3] = {(tile % ntx) * TX, ((tile / ntx) % nty) * TY, (tile / (ntx * nty)) * TZ};
+    const int tid = threadIdx.x;
+    const int lc[3] = {tid % TX, (tid / TX) % TY, tid / (TX * TY)};
+    const int64_t N = g.npts;
+    const bool inside = t0[0] + lc[0] < g.n[0] && t0[1] + lc[1] < g.n[1] && t0[2] + lc[2] < g.n[2];
+    const int64_t p = inside ? (t0[0] + lc[0]) * g.stride[0] + (t0[1] + lc[1]) * g.stride[1] +
+                                   (t0[2] + lc[2]) * g.stride[2]
+                             : 0;
+    const bool active = inside && (g.cls[p] & 15) != CLS_HOLE;
+    Vec<4> own;
+    if (active) {
+        double qq[5];
+        load_q<3>(q, N, p, qq);
+        own = prim<3>(qq, gm1);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) own.v[a] = 0.0;
+    }
+    Vec<4> dxi[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        int ext[3];
+        C::ext(m, ext);
+        {
+            // a tile slot past the grid's end holds the wrapped point of a
+            // periodic direction m (zero otherwise)
+            const int co[3] = {lc[0] + (m == 0 ? R : 0), lc[1] + (m == 1 ? R : 0), lc[2] + (m == 2 ? R : 0)};
+            const int e = co[0] + ext[0] * (co[1] + ext[1] * co[2]);
+            Vec<4> w = own;
+            int64_t idx;
+            if (!inside && C::global(g, t0, m, co, idx) && (g.cls[idx] & 15) != CLS_HOLE) {
+                double qq[5];
+                load_q<3>(q, N, idx, qq);
+                w = prim<3>(qq, gm1);
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a) sW[a][e] = w.v[a];
+        }
+        const int nh = 2 * R * C::NT / C::T(m);
+        for (int h = tid; h < nh; h += C::NT) {
+            int c[3];
+            C::halo(m, h, c);
+            int64_t idx;
+            const bool ok = C::global(g, t0, m, c, idx);
+            Vec<4> w;
+            if (ok && (g.cls[idx] & 15) != CLS_HOLE) {
+                double qq[5];
+                load_q<3>(q, N, idx, qq);
+                w = prim<3>(qq, gm1);
+            } else {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) w.v[a] = 0.0;
+            }
+            const int e = c[0] + ext[0] * (c[1] + ext[1] * c[2]);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) sW[a][e] = w.v[a];
+        }
+        __syncthreads();
+        if (active) {
+            const int base = (lc[0] + (m == 0 ? R : 0)) + ext[0] * ((lc[1] + (m == 1 ? R : 0)) + ext[1] * (lc[2] + (m == 2 ? R : 0)));
+            const int step = m == 0 ? 1 : (m == 1 ? ext[0] : ext[0] * ext[1]);
+            dxi[m] = dsbp<SBP, 4>(g.cls[m * N + p] & 15, [&](int o) {
+                Vec<4> x;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) x.v[a] = sW[a][base + o * step];
+                return x;
+            });
+        }
+        __syncthreads();
+    }
+    if (!inside) return;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) grad[(int64_t)(a * 3 + j) * N + p] = active ? g.inv_h[j] * dxi[j].v[a] : 0.0;
+}
+
+// 3D Cartesian flux divergence + SAT + AB on tiles, from the gradients of the
+// gradient pass: the formulas of k_rhs, each directional flux computed about
+// 1 + 2R / T_m times per output instead of once per stencil entry
+template <int SBP, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(TX * TY * TZ) k_rhs_tile3d(GridDev g, Phys ph, const double *__restrict__ q,
+                                                             const double *__restrict__ grad,
+                                                             double *__restrict__ F, Combine cb, int ntx, int nty,
+                                                             int ntz)
+{
+    constexpr int NV = 5, R = SBP == 21 ? 1 : 3;
+    using C = Tile3<TX, TY, TZ, R>;
+    __shared__ double sF[NV][C::RMAX];
+    const int tile = xcd_tile(blockIdx.x, ntx * nty * ntz);
+    const int t0[3] = {(tile % ntx) * TX, ((tile / ntx) % nty) * TY, (tile / (ntx * nty)) * TZ};
+    const int tid = threadIdx.x;
+    const int lc[3] = {tid % TX, (tid / TX) % TY, tid / (TX * TY)};
+    const int64_t N = g.npts;
+    const bool inside = t0[0] + lc[0] < g.n[0] && t0[1] + lc[1] < g.n[1] && t0[2] + lc[2] < g.n[2];
+    const int64_t p = inside ? (t0[0] + lc[0]) * g.stride[0] + (t0[1] + lc[1]) * g.stride[1] +
+                                   (t0[2] + lc[2]) * g.stride[2]
+                             : 0;
+    const bool active = inside && (g.cls[p] & 15) != CLS_HOLE;
+    Vec<NV> own[3];
+    if (active) {
+        fluxes3(g, ph, q, grad, p, own);
+    } else {
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) own[m].v[v] = 0.0;
+    }
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        int ext[3];
+        C::ext(m, ext);
+        const int co[3] = {lc[0] + (m == 0 ? R : 0), lc[1] + (m == 1 ? R : 0), lc[2] + (m == 2 ? R : 0)};
+        const int base = co[0] + ext[0] * (co[1] + ext[1] * co[2]);
+        {
+            // a tile slot past the grid's end holds the wrapped point of a
+            // periodic direction m (zero otherwise)
+            Vec<NV> f = own[m];
+            int64_t idx;
+            if (!inside && C::global(g, t0, m, co, idx) && (g.cls[idx] & 15) != CLS_HOLE)
+                f = fhat_at<3, 1>(g, ph, q, grad, m, idx);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sF[v][base] = f.v[v];
+        }
+        const int nh = 2 * R * C::NT / C::T(m);
+        for (int h = tid; h < nh; h += C::NT) {
+            int c[3];
+            C::halo(m, h, c);
+            int64_t idx;
+            const bool ok = C::global(g, t0, m, c, idx);
+            Vec<NV> f;
+            if (ok && (g.cls[idx] & 15) != CLS_HOLE) {
+                f = fhat_at<3, 1>(g, ph, q, grad, m, idx);
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) f.v[v] = 0.0;
+            }
+            const int e = c[0] + ext[0] * (c[1] + ext[1] * c[2]);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sF[v][e] = f.v[v];
+        }
+        __syncthreads();
+        if (active) {
+            const int step = m == 0 ? 1 : (m == 1 ? ext[0] : ext[0] * ext[1]);
+            Vec<NV> d = dsbp<SBP, NV>(g.cls[m * N + p] & 15, [&](int o) {
+                Vec<NV> x;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) x.v[v] = sF[v][base + o * step];
+                return x;
+            });
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] += g.inv_h[m] * d.v[v];
+        }
+        __syncthreads();
+    }
+    if (!inside) return;
+    double r[NV];
+    if (active) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) r[v] = -1.0 * acc[v];
+        sat_point<3, 1>(g, ph, q, grad, p, r);
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) r[v] = 0.0;
+    }
+    store_step<3>(q, F, cb, N, p, r);
 }
 
 // ------------------------------------------- fused LDS-tiled 2D right-hand side
@@ -259,14 +519,6 @@ __device__ __forceinline__ int wrap1(int i, int n)
         if (i < 0) i += n;
     }
     return i;
-}
-
-// XCD-aware order: consecutive workgroups go to different XCDs, so give each
-// XCD a contiguous range of tiles (neighbours share halos in its L2); a
-// bijection when the tile count is a multiple of 8, identity otherwise
-__device__ __forceinline__ int xcd_tile(int b, int nblk)
-{
-    return (nblk % 8) ? b : (b % 8) * (nblk / 8) + b / 8;
 }
 
 // the work of one workgroup: the tile with corner (x0, y0) of grid g
@@ -1130,6 +1382,39 @@ hipError_t launch_rhs_tile2d(const GridDev &g, int sbp, const Phys &ph, const do
 
 #define DISPATCH_GRAD(DIM, SBP, CART) \
     hipLaunchKernelGGL((k_grad<DIM, SBP, CART>), dim3(nblk(g.npts, 256)), dim3(256), 0, st, g, gm1, q, grad)
+
+const TileShape3 kTile3dShapes[NUM_TILE3D_SHAPES] = {{8, 8, 8}, {16, 8, 4}, {32, 4, 4}, {16, 4, 4}};
+
+template <int TX, int TY, int TZ>
+static hipError_t tile3d_shape(const GridDev &g, int sbp, const Phys &ph, const double *q, double *grad,
+                               double *F, const Combine &cb, hipStream_t st)
+{
+    const int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY, ntz = (g.n[2] + TZ - 1) / TZ;
+    const dim3 grid((unsigned)(ntx * nty * ntz)), block(TX * TY * TZ);
+    const double gm1 = ph.gamma - 1.0;
+    double *gw = grad;
+    if (sbp == 21) {
+        hipLaunchKernelGGL((k_grad_tile3d<21, TX, TY, TZ>), grid, block, 0, st, g, gm1, q, gw, ntx, nty, ntz);
+        hipLaunchKernelGGL((k_rhs_tile3d<21, TX, TY, TZ>), grid, block, 0, st, g, ph, q, grad, F, cb, ntx, nty, ntz);
+    } else {
+        hipLaunchKernelGGL((k_grad_tile3d<42, TX, TY, TZ>), grid, block, 0, st, g, gm1, q, gw, ntx, nty, ntz);
+        hipLaunchKernelGGL((k_rhs_tile3d<42, TX, TY, TZ>), grid, block, 0, st, g, ph, q, grad, F, cb, ntx, nty, ntz);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_tile3d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *grad,
+                             double *F, const Combine &cb, int shape, hipStream_t st)
+{
+    if (g.dim != 3 || !g.cartesian || (sbp != 21 && sbp != 42)) return hipErrorInvalidValue;
+    switch (shape) {
+    case 0: return tile3d_shape<8, 8, 8>(g, sbp, ph, q, grad, F, cb, st);
+    case 1: return tile3d_shape<16, 8, 4>(g, sbp, ph, q, grad, F, cb, st);
+    case 2: return tile3d_shape<32, 4, 4>(g, sbp, ph, q, grad, F, cb, st);
+    case 3: return tile3d_shape<16, 4, 4>(g, sbp, ph, q, grad, F, cb, st);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_grad(const GridDev &g, int sbp, double gm1, const double *q, double *grad, hipStream_t st)
 {

@@ -230,4 +230,12 @@ __device__ __forceinline__ double add_nc(double acc, double c, double f)
     return acc + t;
 }
 
+// XCD-aware order: consecutive workgroups go to different XCDs, so give each
+// XCD a contiguous range of tiles (neighbours share halos in its L2); a
+// bijection when the tile count is a multiple of 8, identity otherwise
+__device__ __forceinline__ int xcd_tile(int b, int nblk)
+{
+    return (nblk % 8) ? b : (b % 8) * (nblk / 8) + b / 8;
+}
+
 }  // namespace mrk

@@ -30,19 +30,25 @@ def small():
     return workloads.tgv3d(nbg=48, npatch=24, ninner=16)
 
 
-def test_rhs_parity_3d(torch):
+@pytest.mark.parametrize("tile3d", [-1, 0, 1, 2, 3])
+def test_rhs_parity_3d(torch, tile3d):
+    """Point-wise flux kernel (-1) and every LDS tile shape of the 3D flux
+    pass (the 32-wide and 4-deep tiles leave partial tiles on these grids)."""
     from oracle import OracleSystem
     from paper_1805_06607_amd.system import System
     wl = small()
     states = workloads.random_state_like(wl, seed=9, amp=0.02)
     orc = OracleSystem(wl)
     want = orc.rhs(states)
-    got = System(wl).rhs(states)
+    sysg = System(wl)
+    sysg.set_option("rhs_tile3d", tile3d)
+    got = sysg.rhs(states)
     for g in range(len(wl.grids)):
         act = orc.grids[g].iblank.astype(bool)
         e = rel_l2(_np(got[g]), want[g], act)
-        _say("3d rhs", g, e)
+        _say("3d rhs", tile3d, g, e)
         assert np.all(e <= 1e-12), (g, e)
+        assert np.all(_np(got[g])[:, ~act] == 0.0)
 
 
 def test_receiver_data_parity_3d(torch):
