@@ -72,8 +72,9 @@ def run_tgv3d(args):
     # launch durations from a single-stream pass (on the per-grid streams the
     # grids' launches overlap and each event pair would also time the others)
     s.set_option("multi_stream", 0)
-    roof = timed_pass(s, wl, n_act, args.steps, "gradient pass + point-wise right-hand side with fused AB "
-                                                "update (k_grad + k_rhs), all grids' launches of a macrostep")
+    roof = timed_pass(s, wl, n_act, args.steps, "gradient pass + flux divergence, SAT and fused AB update on "
+                                                "LDS tiles (k_grad_tile3d + k_rhs_tile3d), all grids' launches "
+                                                "of a macrostep")
     line = {"metric": "MRAB pt-updates/s (3D three-level case), 1 GPU", "value": pts * args.steps / el,
             "unit": "pt-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "dtype": "f64", "data": "synthetic",

@@ -249,7 +249,7 @@ int mr_kernel_time(mr_ctx *ctx, double *total_ms, int *count);
  *                        tiles of shape 0..3 (8x8x8, 16x8x4, 32x4x4, 16x4x4
  *                        outputs; each thread evaluates its own point once,
  *                        the halo slabs are evaluated per direction), or -1
- *                        for the point-wise kernels (default 0).  Same
+ *                        for the point-wise kernels (default 1).  Same
  *                        formulas; results agree to rounding.
  *  "graph"               reserved: 1 (replaying captured HIP graphs of whole
  *                        macrostep periods) is switched off and returns

@@ -144,7 +144,7 @@ struct mr_ctx {
     std::vector<int> tgrid_of;                // grid of each timed launch
     bool two_pass = false;    // 2D: use the two-kernel (gradient pass) right-hand side
     bool donor_blocks = true; // one-launch donor data for links whose chunks fit one workgroup
-    int tile3d = 0;           // 3D flux pass: LDS tile shape (mrk::kTile3dShapes), -1 the per-point kernel
+    int tile3d = 1;           // 3D passes: LDS tile shape (mrk::kTile3dShapes), -1 the per-point kernels
     int period = 1;                            // macrosteps after which every pointer repeats
     int64_t version = 0;                       // bumped when a batch's launch plan must be rebuilt
     // macrosteps: one stream per grid, ordered by events (Order); -1: when
