@@ -16,7 +16,9 @@ namespace mrk {
 //   point: the local Jacobians of the fluxes and SAT penalties at the point
 //          (forward-mode dual numbers) -> direct adjoint of q (lqd), adjoint
 //          of the index-space derivatives of the primitives (kap), adjoint of
-//          the receiver row;
+//          the receiver row; points without SAT faces one lane each, the SAT
+//          points (listed) one lane per (point, input direction), then one
+//          lane per SAT point collects;
 //   grad:  kap gathered through the transposed gradient rows and the
 //          primitive map's Jacobian -> lam_q.
 struct AdjRhs {
@@ -29,6 +31,9 @@ struct AdjRhs {
     double *lqd;            // nv x N scratch
     double *lam_recv;       // rows x (nv + dim (nv-1)), written at receiver rows
     double *lam_q;          // nv x N, accumulated
+    const int32_t *bpts;    // the nb points ending a run in some direction (SAT points)
+    int nb;
+    double *bres;           // nb x (nv + dim (dim+1) + nv + dim (nv-1)) scratch
 };
 
 // Adjoint of one link's donor data at one time: the receiving grid's
@@ -79,6 +84,18 @@ hipError_t launch_adj_rhs(const AdjRhs &a, int sbp, hipStream_t st);
 hipError_t launch_adj_donor(const AdjDonor &a, int sbp, hipStream_t st);
 hipError_t launch_obj(const Objective &o, const double *y, int64_t N, double tau, double *acc, hipStream_t st);
 hipError_t launch_obj_adj(const Objective &o, const double *y, int64_t N, double tau, double *lam, hipStream_t st);
+// adjoint of an extrapolant ext = y + sum_h beta_h hist_h at listed points:
+// lam_y += lam_ext, lam_hist[h] += beta_h lam_ext, then lam_ext = 0 there
+struct AdjExt {
+    double *lam_ext, *lam_y;
+    double *lam_hist[MAXH];
+    double beta[MAXH];
+    int m, nv;
+    int64_t N;
+    const int32_t *pts;
+    int64_t np;
+};
+hipError_t launch_adj_ext(const AdjExt &a, hipStream_t st);
 // dst[i][e] += coef[i] * src[e] for i < nd, e < n
 hipError_t launch_adj_axpy(int64_t n, const double *src, int nd, double *const *dst, const double *coef,
                            hipStream_t st);

@@ -332,81 +332,68 @@ __global__ void __launch_bounds__(256) k_adj_flux(AdjRhs a)
     }
 }
 
+// the local Jacobian products at point x for input direction i (inputs: q,
+// then the gradients (u, v, T) x (x, y), then the receiver row): flux terms
+// weighted by mu, SAT terms (when sat) weighted by the right-hand-side
+// adjoint at x
 template <int DIM, int SBP, int CART>
-__global__ void __launch_bounds__(256) k_adj_point(AdjRhs a)
+__device__ __forceinline__ void point_inputs(const AdjRhs &a, int64_t x, double *qx, double (*gr)[DIM])
+{
+    const int64_t N = a.g.npts;
+    int ic[3];
+    coords(a.g, x, ic);
+    load_q<DIM>(a.q, N, x, qx);
+    gradient<DIM, SBP, CART>(a.g, x, ic, a.ph.gamma - 1.0, [&](int64_t idx, double *o) { load_q<DIM>(a.q, N, idx, o); },
+                             gr);
+}
+
+template <int DIM, int CART>
+__device__ __forceinline__ double point_seed(const AdjRhs &a, int64_t x, const double *qx, const double (*gr)[DIM],
+                                             int i, bool sat, bool iface)
 {
     constexpr int NV = DIM + 2, NG = (DIM + 1) * DIM, RB = NV + DIM * (NV - 1);
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const GridDev &g = a.g;
     const int64_t N = g.npts;
-    if (x >= N) return;
-    if (hole(g, x)) {
-        for (int v = 0; v < NV; ++v) a.lqd[v * N + x] = 0.0;
-        for (int k = 0; k < NG; ++k) a.kap[k * N + x] = 0.0;
-        return;
-    }
-    const double gm1 = a.ph.gamma - 1.0;
-    int ic[3];
-    coords(g, x, ic);
-    double qx[NV];
-    load_q<DIM>(a.q, N, x, qx);
-    double gr[DIM + 1][DIM];
-    gradient<DIM, SBP, CART>(g, x, ic, gm1, [&](int64_t idx, double *o) { load_q<DIM>(a.q, N, idx, o); }, gr);
-    double A[DIM][DIM];
+    Dual qd[NV], grd[DIM + 1][DIM];
 #pragma unroll
-    for (int m = 0; m < DIM; ++m)
+    for (int v = 0; v < NV; ++v) qd[v] = Dual(qx[v], i == v ? 1.0 : 0.0);
 #pragma unroll
-        for (int j = 0; j < DIM; ++j)
-            A[m][j] = CART ? (j == m ? 1.0 : 0.0) : g.metric[(int64_t)(m * DIM + j) * N + x];
-    double mu[DIM][NV];
+    for (int b = 0; b <= DIM; ++b)
 #pragma unroll
-    for (int m = 0; m < DIM; ++m)
+        for (int j = 0; j < DIM; ++j) grd[b][j] = Dual(gr[b][j], i == NV + b * DIM + j ? 1.0 : 0.0);
+    double s = 0.0;
+    if (i < NV + NG) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) mu[m][v] = a.mu[(int64_t)(m * NV + v) * N + x];
-    bool anyb = false, iface = false;
+        for (int m = 0; m < DIM; ++m) {
+            double A[DIM];
 #pragma unroll
-    for (int m = 0; m < DIM; ++m) {
-        const int bc = (g.cls[m * N + x] >> 4) & 3;
-        anyb |= bc != 0;
-        iface |= bc == 1;
-    }
-    double lf[NV], rbv[RB];
+            for (int j = 0; j < DIM; ++j) A[j] = CART ? (j == m ? 1.0 : 0.0) : g.metric[(int64_t)(m * DIM + j) * N + x];
+            Dual out[NV];
+            flux_t<DIM, Dual>(a.ph, qd, grd, A, out);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) lf[v] = anyb ? a.lamF[v * N + x] : 0.0;
-    const int64_t row = iface ? g.recv_idx[x] : -1;
-#pragma unroll
-    for (int t = 0; t < RB; ++t) rbv[t] = iface ? g.recv[row * RB + t] : 0.0;
-    const int nin = NV + NG + (iface ? RB : 0);
-    double res[NV + NG + RB];
-#pragma unroll 1
-    for (int i = 0; i < nin; ++i) {
-        Dual qd[NV], grd[DIM + 1][DIM], rbd[RB];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) qd[v] = Dual(qx[v], i == v ? 1.0 : 0.0);
-#pragma unroll
-        for (int b = 0; b <= DIM; ++b)
-#pragma unroll
-            for (int j = 0; j < DIM; ++j) grd[b][j] = Dual(gr[b][j], i == NV + b * DIM + j ? 1.0 : 0.0);
-#pragma unroll
-        for (int t = 0; t < RB; ++t) rbd[t] = Dual(rbv[t], i == NV + NG + t ? 1.0 : 0.0);
-        double s = 0.0;
-        if (i < NV + NG) {
-#pragma unroll
-            for (int m = 0; m < DIM; ++m) {
-                Dual out[NV];
-                flux_t<DIM, Dual>(a.ph, qd, grd, A[m], out);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) s += mu[m][v] * out[v].d;
-            }
+            for (int v = 0; v < NV; ++v) s += a.mu[(int64_t)(m * NV + v) * N + x] * out[v].d;
         }
-        if (anyb) {
-            Dual r[NV];
-            sat_t<DIM, CART, Dual>(g, a.ph, x, qd, grd, rbd, r);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) s += lf[v] * r[v].d;
-        }
-        res[i] = s;
     }
+    if (sat) {
+        Dual rbd[RB];
+        const double *rb = iface ? g.recv + (int64_t)g.recv_idx[x] * RB : nullptr;
+#pragma unroll
+        for (int t = 0; t < RB; ++t) rbd[t] = Dual(iface ? rb[t] : 0.0, i == NV + NG + t ? 1.0 : 0.0);
+        Dual r[NV];
+        sat_t<DIM, CART, Dual>(g, a.ph, x, qd, grd, rbd, r);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s += a.lamF[v * N + x] * r[v].d;
+    }
+    return s;
+}
+
+// results of the local Jacobians at x -> lqd, kap (and the receiver row)
+template <int DIM, int CART>
+__device__ __forceinline__ void point_store(const AdjRhs &a, int64_t x, const double *res, bool iface)
+{
+    constexpr int NV = DIM + 2, NG = (DIM + 1) * DIM, RB = NV + DIM * (NV - 1);
+    const GridDev &g = a.g;
+    const int64_t N = g.npts;
 #pragma unroll
     for (int v = 0; v < NV; ++v) a.lqd[v * N + x] = res[v];
     const double Jx = CART ? 1.0 : g.metric[(int64_t)(DIM * DIM) * N + x];
@@ -420,13 +407,92 @@ __global__ void __launch_bounds__(256) k_adj_point(AdjRhs a)
             } else {
                 k = 0.0;
 #pragma unroll
-                for (int j = 0; j < DIM; ++j) k += A[m][j] * res[NV + b * DIM + j];
+                for (int j = 0; j < DIM; ++j) k += g.metric[(int64_t)(m * DIM + j) * N + x] * res[NV + b * DIM + j];
                 k *= Jx;
             }
             a.kap[(int64_t)(m * (DIM + 1) + b) * N + x] = k;
         }
-    if (iface)
+    if (iface) {
+        const int64_t row = g.recv_idx[x];
         for (int t = 0; t < RB; ++t) a.lam_recv[row * RB + t] = res[NV + NG + t];
+    }
+}
+
+__device__ __forceinline__ void bc_flags(const GridDev &g, int dim, int64_t x, bool &anyb, bool &iface)
+{
+    anyb = iface = false;
+    for (int m = 0; m < dim; ++m) {
+        const int bc = (g.cls[m * g.npts + x] >> 4) & 3;
+        anyb |= bc != 0;
+        iface |= bc == 1;
+    }
+}
+
+// points without a SAT face (holes: zeros); SAT points are left to the
+// listed kernels below
+template <int DIM, int SBP, int CART>
+__global__ void __launch_bounds__(256) k_adj_point(AdjRhs a)
+{
+    constexpr int NV = DIM + 2, NG = (DIM + 1) * DIM;
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const GridDev &g = a.g;
+    const int64_t N = g.npts;
+    if (x >= N) return;
+    if (hole(g, x)) {
+        for (int v = 0; v < NV; ++v) a.lqd[v * N + x] = 0.0;
+        for (int k = 0; k < NG; ++k) a.kap[k * N + x] = 0.0;
+        return;
+    }
+    bool anyb, iface;
+    bc_flags(g, DIM, x, anyb, iface);
+    if (anyb) return;
+    double qx[NV], gr[DIM + 1][DIM];
+    point_inputs<DIM, SBP, CART>(a, x, qx, gr);
+    double res[NV + NG];
+#pragma unroll 1
+    for (int i = 0; i < NV + NG; ++i) {
+        const double s = point_seed<DIM, CART>(a, x, qx, gr, i, false, false);
+#pragma unroll
+        for (int k = 0; k < NV + NG; ++k)
+            if (k == i) res[k] = s;
+    }
+    point_store<DIM, CART>(a, x, res, false);
+}
+
+// SAT points: one lane per (listed point, input direction)
+template <int DIM, int SBP, int CART>
+__global__ void __launch_bounds__(256) k_adj_bnd(AdjRhs a)
+{
+    constexpr int NV = DIM + 2, NG = (DIM + 1) * DIM, RB = NV + DIM * (NV - 1), NIN = NV + NG + RB;
+    const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = lane / NIN;
+    const int i = (int)(lane % NIN);
+    if (b >= a.nb) return;
+    const int64_t x = a.bpts[b];
+    bool anyb, iface;
+    bc_flags(a.g, DIM, x, anyb, iface);
+    double s = 0.0;
+    if (i < NV + NG || iface) {
+        double qx[NV], gr[DIM + 1][DIM];
+        point_inputs<DIM, SBP, CART>(a, x, qx, gr);
+        s = point_seed<DIM, CART>(a, x, qx, gr, i, true, iface);
+    }
+    a.bres[lane] = s;
+}
+
+template <int DIM, int CART>
+__global__ void __launch_bounds__(256) k_adj_bnd_store(AdjRhs a)
+{
+    constexpr int NV = DIM + 2, NG = (DIM + 1) * DIM, RB = NV + DIM * (NV - 1), NIN = NV + NG + RB;
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.nb) return;
+    const int64_t x = a.bpts[b];
+    bool anyb, iface;
+    bc_flags(a.g, DIM, x, anyb, iface);
+    double res[NIN];
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) res[k] = a.bres[b * NIN + k];
+    point_store<DIM, CART>(a, x, res, iface);
 }
 
 // adjoint of the primitives at one state -> adjoint of q
@@ -621,6 +687,18 @@ __global__ void __launch_bounds__(256) k_obj_adj(Objective o, int dim, const dou
     lam[(dim + 1) * N + p] += f;
 }
 
+__global__ void __launch_bounds__(256) k_adj_ext(AdjExt a)
+{
+    const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (lane >= a.np * a.nv) return;
+    const int v = (int)(lane / a.np);
+    const int64_t el = (int64_t)v * a.N + a.pts[lane - (int64_t)v * a.np];
+    const double l = a.lam_ext[el];
+    a.lam_y[el] += l;
+    for (int h = 0; h < a.m; ++h) a.lam_hist[h][el] += a.beta[h] * l;
+    a.lam_ext[el] = 0.0;
+}
+
 struct AxpyList {
     int nd;
     double *dst[MAXH + 2];
@@ -644,6 +722,11 @@ static hipError_t adj_rhs_t(const AdjRhs &a, hipStream_t st)
     const unsigned nb = nblk_(a.g.npts, 256);
     hipLaunchKernelGGL((k_adj_flux<2, SBP, CART>), dim3(nb), dim3(256), 0, st, a);
     hipLaunchKernelGGL((k_adj_point<2, SBP, CART>), dim3(nb), dim3(256), 0, st, a);
+    if (a.nb > 0) {
+        constexpr int NIN = 4 + 6 + 10;
+        hipLaunchKernelGGL((k_adj_bnd<2, SBP, CART>), dim3(nblk_((int64_t)a.nb * NIN, 256)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_adj_bnd_store<2, CART>), dim3(nblk_(a.nb, 256)), dim3(256), 0, st, a);
+    }
     hipLaunchKernelGGL((k_adj_grad<2, SBP, CART>), dim3(nb), dim3(256), 0, st, a);
     return hipGetLastError();
 }
@@ -682,6 +765,14 @@ hipError_t launch_obj_adj(const Objective &o, const double *y, int64_t N, double
 {
     if (o.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_obj_adj, dim3(nblk_(o.n, 256)), dim3(256), 0, st, o, 2, y, N, tau, lam);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_ext(const AdjExt &a, hipStream_t st)
+{
+    if (a.m < 0 || a.m > MAXH) return hipErrorInvalidValue;
+    if (a.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_ext, dim3(nblk_(a.np * a.nv, 256)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -1224,6 +1224,9 @@ struct AdjGrid {
     double *snap = nullptr;                        // nsnap x (1 + m) states
     double *boot = nullptr;                        // nboot + 1 bootstrap states
     double *stg[4] = {}, *kk[4] = {}, *lk[4] = {}; // bootstrap stage states, derivatives, adjoints
+    std::vector<int32_t> bpts;                     // points ending a run in some direction
+    int32_t *bpts_d = nullptr;
+    double *bres = nullptr;                        // their local-Jacobian results
 };
 
 struct AdjCtx {
@@ -1301,6 +1304,18 @@ void adj_tables(mr_ctx *c)
             i = k;
         }
     }
+    A.G.resize(c->G.size());
+    for (size_t gi = 0; gi < c->G.size(); ++gi) {
+        const GridHost &g = c->G[gi];
+        std::vector<int32_t> &B = A.G[gi].bpts;
+        B.clear();
+        for (int64_t p = 0; p < g.npts; ++p) {
+            if ((g.cls[p] & 15) == mrk::CLS_HOLE) continue;
+            bool any = false;
+            for (int d = 0; d < g.dim; ++d) any = any || ((g.cls[(size_t)d * g.npts + p] >> 4) & 3) != 0;
+            if (any) B.push_back((int32_t)p);
+        }
+    }
     A.tables = true;
 }
 
@@ -1337,6 +1352,10 @@ size_t adj_layout(mr_ctx *c, char *base)
             a.kk[k] = st();
             a.lk[k] = st();
         }
+        const size_t nv = g.dim + 2, ng = (size_t)g.dim * (g.dim + 1), rb = nv + (size_t)g.dim * (nv - 1);
+        const size_t nin = nv + ng + rb;      // inputs of a SAT point's local Jacobian
+        a.bpts_d = cv.take<int32_t>(a.bpts.size() + 1);
+        a.bres = cv.take<double>(a.bpts.size() * nin + 1);
     }
     for (size_t li = 0; li < c->links.size(); ++li) {
         AdjLink &T = A.L[li];
@@ -1420,6 +1439,9 @@ int adj_rhs_rev(mr_ctx *c, int gi, const double *q, double *recv, const double *
     r.lqd = a.lqd;
     r.lam_recv = lam_recv;
     r.lam_q = lam_q;
+    r.bpts = a.bpts_d;
+    r.nb = (int)a.bpts.size();
+    r.bres = a.bres;
     HIPCHK(c, mrk::launch_adj_rhs(r, c->P.sbp, c->st));
     return MR_OK;
 }
@@ -1724,16 +1746,24 @@ int adj_macro_fwd(mr_ctx *c, int n, int nmacro, bool obj)
             const int per_d = c->rmax / D.rate, e = k / per_d, jp = k % per_d;
             const double *Y = gstate(a, D, a.ys, e);
             if (jp) {
+                // the extrapolant at the points the donor kernels read (the
+                // donor grid's stencil closure); other points are not used
                 double *X = gstate(a, D, a.ext, k - 1);
                 if (!made[L.dg]) {
-                    mrk::Combine cb{};
-                    cb.m = m;
+                    mrk::Extrap x{};
+                    x.y = Y;
+                    x.m = m;
+                    x.nv = D.dim + 2;
+                    x.N = D.npts;
                     for (int j = 0; j < m; ++j) {
-                        cb.c[j] = c->beta[L.dg][jp][j];
-                        cb.hist[j] = a.ring[j];
+                        x.hist[j] = a.ring[j];
+                        x.beta[0][j] = c->beta[L.dg][jp][j];
                     }
-                    cb.y_next = X;
-                    HIPCHK(c, mrk::launch_combine(nelem(D), Y, cb, c->st));
+                    x.nj = 1;
+                    x.out[0] = X;
+                    x.pts = D.closure_d;
+                    x.np = (int64_t)D.closure.size();
+                    HIPCHK(c, mrk::launch_extrap(x, c->st));
                     made[L.dg] = true;
                 }
                 Y = X;
@@ -1798,16 +1828,23 @@ int adj_macro_rev(mr_ctx *c, int n, int nmacro, double jscale)
                 if (rc) return rc;
                 continue;
             }
-            HIPCHK(c, hipMemsetAsync(a.lam_ext, 0, nelem(D) * 8, c->st));
+            // lam_ext is zero outside the stencil closure and is cleared there
+            // after each use
             rc = adj_donor_rev(c, li, gstate(a, D, a.ext, k - 1), lr, a.lam_ext);
             if (rc) return rc;
-            std::vector<double *> dst(1, a.lam_y);
-            std::vector<double> coef(1, 1.0);
+            mrk::AdjExt x{};
+            x.lam_ext = a.lam_ext;
+            x.lam_y = a.lam_y;
             for (int j = 0; j < m; ++j) {
-                dst.push_back(a.lam_ring[j]);
-                coef.push_back(c->beta[L.dg][jp][j]);
+                x.lam_hist[j] = a.lam_ring[j];
+                x.beta[j] = c->beta[L.dg][jp][j];
             }
-            HIPCHK(c, mrk::launch_adj_axpy(nelem(D), a.lam_ext, (int)dst.size(), dst.data(), coef.data(), c->st));
+            x.m = m;
+            x.nv = D.dim + 2;
+            x.N = D.npts;
+            x.pts = D.closure_d;
+            x.np = (int64_t)D.closure.size();
+            HIPCHK(c, mrk::launch_adj_ext(x, c->st));
         }
         for (int g = 0; g < G; ++g) {
             if (!ends[g]) continue;
@@ -2837,6 +2874,11 @@ int mr_adj_bind_workspace(mr_ctx *c, void *dev, size_t bytes)
         HIPCHK(c, up(T.cent_d, T.cent));
         HIPCHK(c, up(T.cself_d, T.cself));
     }
+    for (size_t gi = 0; gi < c->G.size(); ++gi) {
+        const AdjGrid &a = A.G[gi];
+        if (!a.bpts.empty())
+            HIPCHK(c, hipMemcpyAsync(a.bpts_d, a.bpts.data(), a.bpts.size() * 4, hipMemcpyHostToDevice, c->st));
+    }
     A.snap_pos.assign(A.nsnap, -1);
     A.bound = true;
     int rc = adj_upload_objective(c);
@@ -2920,6 +2962,7 @@ int mr_adj_gradient(mr_ctx *c, int nmacro, const double *const *y0, const double
         else
             HIPCHK(c, hipMemsetAsync(A.G[g].lam_y, 0, nb, c->st));
         for (int j = 0; j < m; ++j) HIPCHK(c, hipMemsetAsync(A.G[g].lam_ring[j], 0, nb, c->st));
+        HIPCHK(c, hipMemsetAsync(A.G[g].lam_ext, 0, nb, c->st));
     }
     if (nmacro > 0) {
         Sched S;
