@@ -460,12 +460,15 @@ def run_gpu(args):
 
 
 def equal_error(args, h):
-    """MRAB (macrostep 4h, O-mesh at h) and single-rate AB (every grid at h)
-    against a single-rate reference at h/4, all from the same initial state
-    and stopped at the same final time T = 4h (m - 1 + N) (each bootstrap
-    spans m - 1 of its own macrosteps); error = max |rho - rho_ref| over
-    active points of both grids (the paper's error measure for its
-    convergence tables).  Wall time covers the macrosteps only."""
+    """MRAB (macrostep 4 hh, O-mesh at hh) and single-rate AB (every grid at
+    hh) for hh in {h, h/2, h/4}, against a single-rate reference at h/16, all
+    from the same initial state and stopped at the same final time T = 4h (m -
+    1 + N) (each bootstrap spans m - 1 of its own macrosteps); error = max |rho
+    - rho_ref| over active points of both grids (the paper's error measure
+    for its convergence tables).  Wall time covers the macrosteps only.  The
+    claim checked: MRAB's error-versus-wall-time curve lies below single-rate
+    AB's (log-log interpolation of the single-rate curve at MRAB's wall
+    times)."""
     import torch
     from paper_1805_06607_amd.system import System
     N = args.ee_macrosteps
@@ -490,6 +493,7 @@ def equal_error(args, h):
         wl.params["dt_fixed"] = H
         s = System(wl)
         s.timestep()
+        s.autotune(reps=10)
         s.start(0.0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -502,19 +506,41 @@ def equal_error(args, h):
         del s
         return rho, ib, el, t
 
-    ref, ib, el_ref, t_ref = run((1, 1), h / 4, 15 * (m - 1) + 16 * N)
-    rho_m, _, el_m, t_m = run((1, 4), 4 * h, N)
-    rho_s, _, el_s, t_s = run((1, 1), h, 3 * (m - 1) + 4 * N)
+    ref, ib, el_ref, t_ref = run((1, 1), h / 16, 63 * (m - 1) + 64 * N)
 
     def err(rho):
         return max(float(np.max(np.abs(rho[g] - ref[g])[ib[g]])) for g in range(2))
 
-    e_m, e_s = err(rho_m), err(rho_s)
-    log(f"equal error: T={t_ref:.6g} (mrab {t_m:.6g}, srab {t_s:.6g}); err mrab {e_m:.3e} srab {e_s:.3e}; "
-        f"wall mrab {el_m:.4f}s srab {el_s:.4f}s")
-    return {"T": t_ref, "mrab_macrosteps": N, "spinup_steps_at_h_over_4": args.ee_spinup, "err_mrab": e_m, "err_srab": e_s,
-            "wall_s_mrab": el_m, "wall_s_srab": el_s, "wall_ratio_srab_over_mrab": el_s / el_m,
-            "reference": "single-rate AB at h/4", "error": "max |rho - rho_ref| over active points"}
+    pts = []
+    for f in (1, 2, 4):
+        hh = h / f
+        Nh = f * (N + m - 1) - (m - 1)
+        rho_m, _, el_m, t_m = run((1, 4), 4 * hh, Nh)
+        rho_s, _, el_s, t_s = run((1, 1), hh, 3 * (m - 1) + 4 * Nh)
+        pts.append({"h": hh, "mrab_macrosteps": Nh, "err_mrab": err(rho_m), "err_srab": err(rho_s),
+                    "wall_s_mrab": el_m, "wall_s_srab": el_s, "T_mrab": t_m, "T_srab": t_s})
+        log(f"equal error h/{f}: err mrab {pts[-1]['err_mrab']:.3e} srab {pts[-1]['err_srab']:.3e}; "
+            f"wall mrab {el_m:.4f}s srab {el_s:.4f}s")
+    # single-rate error at MRAB's wall times (log-log interpolation, clamped to
+    # the measured range) over MRAB's error: > 1 where MRAB is below the curve
+    lw = np.log([p["wall_s_srab"] for p in pts])
+    le = np.log([p["err_srab"] for p in pts])
+    order = np.argsort(lw)
+    below = []
+    for p in pts:
+        x = np.log(p["wall_s_mrab"])
+        e_s = float(np.exp(np.interp(x, lw[order], le[order])))
+        below.append(e_s / p["err_mrab"])
+    first = pts[0]
+    log(f"equal error: T={t_ref:.6g}; single-rate error at MRAB's wall time / MRAB error = "
+        + ", ".join(f"{b:.2f}" for b in below))
+    return {"T": t_ref, "mrab_macrosteps": N, "spinup_steps_at_h_over_4": args.ee_spinup,
+            "err_mrab": first["err_mrab"], "err_srab": first["err_srab"],
+            "wall_s_mrab": first["wall_s_mrab"], "wall_s_srab": first["wall_s_srab"],
+            "wall_ratio_srab_over_mrab": first["wall_s_srab"] / first["wall_s_mrab"],
+            "curve": pts, "srab_err_at_mrab_wall_over_mrab_err": below,
+            "mrab_curve_below_srab": bool(all(b > 1.0 for b in below)),
+            "reference": "single-rate AB at h/16", "error": "max |rho - rho_ref| over active points"}
 
 
 def cpu_baseline(args):
