@@ -7,7 +7,7 @@ def require_gpu():
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    # on a GPU machine the HIP library must be there: import errors are failures
+    # with a GPU present the HIP library must be there: import errors are failures
     from paper_1805_06607_amd import _lib
     _lib.load()
     return torch
