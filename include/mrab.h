@@ -322,9 +322,9 @@ void mr_batch_destroy(mr_batch *batch);
  * of a weighted sum of the pressure p = (gamma - 1)(rho E - rho |u|^2 / 2)
  * at listed points of one grid (a wall-pressure force when w_k = n_x ds).
  * The run the adjoint differentiates is the library's own forward pass of
- * the method: the right-hand sides, AB combinations and extrapolants are the
- * kernels and rounding order of mr_mrab_macrostep; donor data take the
- * two-launch path.  Every step of the derivative is a hand-written adjoint
+ * the method, with the kernels and rounding order of mr_mrab_macrostep (the
+ * fused right-hand side with the next own step, the donor-data launches, the
+ * extrapolants at the donor-stencil points).  Every step of the derivative is a hand-written adjoint
  * kernel (transposed SBP rows as gathers, exact local Jacobians of the
  * pointwise flux, SAT and primitive maps by forward-mode dual numbers,
  * donor data reversed per donor and stencil point from precomputed tables,

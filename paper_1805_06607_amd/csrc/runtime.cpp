@@ -1218,7 +1218,9 @@ struct AdjGrid {
     double *lam_ring[mrk::MAXH] = {};
     double *mu = nullptr, *kap = nullptr, *lqd = nullptr;
     double *recv = nullptr, *lam_recv = nullptr;   // nslice slices of receiver rows
-    double *ys = nullptr;                          // rate + 1 states of one macrostep
+    double *ys = nullptr;                          // rate + 2 states: a macrostep's start, its own-step
+                                                   // states, the next one's first (a ring from ys0)
+    int ys0 = 0;
     double *ring[mrk::MAXH] = {};                  // forward history, oldest first
     double *ext = nullptr;                         // rmax extrapolants (by micro-time)
     double *snap = nullptr;                        // nsnap x (1 + m) states
@@ -1340,7 +1342,7 @@ size_t adj_layout(mr_ctx *c, char *base)
         const size_t rows = g.recv_pts.size() * (size_t)((g.dim + 2) + g.dim * (g.dim + 1));
         a.recv = rows ? cv.take<double>(rows * A.nslice) : nullptr;
         a.lam_recv = rows ? cv.take<double>(rows * A.nslice) : nullptr;
-        a.ys = cv.take<double>(ne * (g.rate + 1));
+        a.ys = cv.take<double>(ne * (g.rate + 2));
         for (int j = 0; j < m; ++j) a.ring[j] = st();
         const bool donor_mid = c->rmax / g.rate > 1 && std::any_of(c->links.begin(), c->links.end(),
                                                                   [&](const Link &L) { return L.dg == (int)gi; });
@@ -1382,6 +1384,9 @@ double *gstate(const AdjGrid &, const GridHost &g, double *base, int i)
 {
     return base + (size_t)i * (g.dim + 2) * g.npts;
 }
+// state after e own steps of the current macrostep (e = 0: its start)
+double *ysl(const AdjGrid &a, const GridHost &g, int e) { return gstate(a, g, a.ys, (a.ys0 + e) % (g.rate + 2)); }
+
 double *rslice(const mr_ctx *c, const GridHost &g, double *base, int s)
 {
     if (!base) return nullptr;
@@ -1399,26 +1404,61 @@ mrk::Objective adj_obj(const mr_ctx *c)
     return o;
 }
 
-// donor data of link L from donor state Y into rows out (two-launch path)
+// donor data of link L from donor state Y into rows out (one launch per
+// chunked link, else values then gather)
 int adj_donor_fwd(mr_ctx *c, const Link &L, const double *Y, double *out)
 {
     mrk::DonorLink a = link_base(c, L);
     a.nj = 1;
     a.ys[0] = Y;
     a.out[0] = out;
-    HIPCHK(c, mrk::launch_donor(a, c->st));
+    if (use_blocks(c, L))
+        HIPCHK(c, mrk::launch_donor_block(a, link_blocks(L), c->st));
+    else
+        HIPCHK(c, mrk::launch_donor(a, c->st));
     return MR_OK;
 }
 
-// right-hand side of grid gi from q with receiver rows recv into F
-int adj_rhs_fwd(mr_ctx *c, int gi, const double *q, double *recv, double *F)
+// right-hand side of grid gi from q with receiver rows recv into F (and the
+// fused AB combination cb when cb.m > 0)
+int adj_rhs_fwd(mr_ctx *c, int gi, const double *q, double *recv, double *F, const mrk::Combine &cb = mrk::Combine{})
 {
     GridHost &g = c->G[gi];
     GridDev dev = g.dev;
     dev.recv = recv;
-    mrk::Combine none{};
-    HIPCHK(c, mrk::launch_rhs_tile2d(dev, c->P.sbp, c->ph, q, F, none, shape_of(g), c->st));
+    HIPCHK(c, mrk::launch_rhs_tile2d(dev, c->P.sbp, c->ph, q, F, cb, shape_of(g), c->st));
     return MR_OK;
+}
+
+// every grid's first own step of the current macrostep from its start and
+// history (the staging mr_mrab_resume does)
+int adj_stage(mr_ctx *c)
+{
+    AdjCtx &A = *c->adj;
+    const int m = c->P.hist_len;
+    for (size_t g = 0; g < c->G.size(); ++g) {
+        const GridHost &Gh = c->G[g];
+        AdjGrid &a = A.G[g];
+        mrk::Combine cb{};
+        cb.m = m;
+        for (int j = 0; j < m; ++j) {
+            cb.c[j] = c->c_own[g][j];
+            cb.hist[j] = a.ring[j];
+        }
+        cb.y_next = ysl(a, Gh, 1);
+        HIPCHK(c, mrk::launch_combine(nelem(Gh), ysl(a, Gh, 0), cb, c->st));
+    }
+    return MR_OK;
+}
+
+// after a macrostep: its end state (and the staged next step) become the
+// next macrostep's start
+void adj_advance(mr_ctx *c)
+{
+    for (size_t g = 0; g < c->G.size(); ++g) {
+        AdjGrid &a = c->adj->G[g];
+        a.ys0 = (a.ys0 + c->G[g].rate) % (c->G[g].rate + 2);
+    }
 }
 
 // lam_q += (dR/dq)^T lamF and lam_recv = (dR/drecv)^T lamF for grid gi
@@ -1604,10 +1644,12 @@ int adj_boot_fwd(mr_ctx *c)
             }
         }
     }
-    for (int g = 0; g < G; ++g)
-        HIPCHK(c, hipMemcpyAsync(A.G[g].ys, gstate(A.G[g], c->G[g], A.G[g].boot, A.nboot), nelem(c->G[g]) * 8,
-                                 hipMemcpyDeviceToDevice, c->st));
-    return MR_OK;
+    for (int g = 0; g < G; ++g) {
+        A.G[g].ys0 = 0;
+        HIPCHK(c, hipMemcpyAsync(ysl(A.G[g], c->G[g], 0), gstate(A.G[g], c->G[g], A.G[g].boot, A.nboot),
+                                 nelem(c->G[g]) * 8, hipMemcpyDeviceToDevice, c->st));
+    }
+    return adj_stage(c);
 }
 
 // bootstrap reverse: on entry lam_y / lam_ring hold the adjoint of the MRAB
@@ -1711,9 +1753,11 @@ int adj_boot_rev(mr_ctx *c)
     return MR_OK;
 }
 
-// one MRAB macrostep (index n of nmacro) from ys[0] and ring[], leaving
-// every own-step state in ys[1..rate], the extrapolants in ext[k-1] and the
-// receiver rows in slice k-1; adds the objective terms when obj
+// one MRAB macrostep (index n of nmacro) from its start (ysl 0, the staged
+// first own step in ysl 1) and ring[], leaving every own-step state in ysl
+// 1..rate, the next macrostep's staged first step in ysl rate + 1, the
+// extrapolants in ext[k-1] and the receiver rows in slice k-1; adds the
+// objective terms when obj.  adj_advance then makes its end the next start.
 int adj_macro_fwd(mr_ctx *c, int n, int nmacro, bool obj)
 {
     AdjCtx &A = *c->adj;
@@ -1721,22 +1765,12 @@ int adj_macro_fwd(mr_ctx *c, int n, int nmacro, bool obj)
     for (int k = 1; k <= c->rmax; ++k) {
         bool ends[mrk::MAXG] = {};
         for (int g = 0; g < G; ++g) ends[g] = k % (c->rmax / c->G[g].rate) == 0;
-        for (int g = 0; g < G; ++g) {
-            if (!ends[g]) continue;
-            const GridHost &Gh = c->G[g];
-            AdjGrid &a = A.G[g];
+        // own steps ending at k were staged by the grid's previous evaluation
+        if (obj && A.og >= 0 && ends[A.og]) {
+            const GridHost &Gh = c->G[A.og];
             const int e = k / (c->rmax / Gh.rate);
-            mrk::Combine cb{};
-            cb.m = m;
-            for (int j = 0; j < m; ++j) {
-                cb.c[j] = c->c_own[g][j];
-                cb.hist[j] = a.ring[j];
-            }
-            cb.y_next = gstate(a, Gh, a.ys, e);
-            HIPCHK(c, mrk::launch_combine(nelem(Gh), gstate(a, Gh, a.ys, e - 1), cb, c->st));
-            if (obj && g == A.og)
-                HIPCHK(c, mrk::launch_obj(adj_obj(c), cb.y_next, Gh.npts, adj_tau(c, n * Gh.rate + e, nmacro), A.acc,
-                                          c->st));
+            HIPCHK(c, mrk::launch_obj(adj_obj(c), ysl(A.G[A.og], Gh, e), Gh.npts, adj_tau(c, n * Gh.rate + e, nmacro),
+                                      A.acc, c->st));
         }
         bool made[mrk::MAXG] = {};
         for (const Link &L : c->links) {
@@ -1744,7 +1778,7 @@ int adj_macro_fwd(mr_ctx *c, int n, int nmacro, bool obj)
             const GridHost &D = c->G[L.dg];
             AdjGrid &a = A.G[L.dg];
             const int per_d = c->rmax / D.rate, e = k / per_d, jp = k % per_d;
-            const double *Y = gstate(a, D, a.ys, e);
+            const double *Y = ysl(a, D, e);
             if (jp) {
                 // the extrapolant at the points the donor kernels read (the
                 // donor grid's stencil closure); other points are not used
@@ -1776,15 +1810,17 @@ int adj_macro_fwd(mr_ctx *c, int n, int nmacro, bool obj)
             const GridHost &Gh = c->G[g];
             AdjGrid &a = A.G[g];
             const int e = k / (c->rmax / Gh.rate);
-            int rc = adj_rhs_fwd(c, g, gstate(a, Gh, a.ys, e), rslice(c, Gh, a.recv, k - 1), a.ring[0]);
+            // the right-hand side into the oldest history slot, fused with the
+            // next own step from the newer slots and the new value
+            mrk::Combine cb{};
+            cb.m = m;
+            for (int j = 0; j < m - 1; ++j) cb.hist[j] = a.ring[j + 1];
+            for (int j = 0; j < m; ++j) cb.c[j] = c->c_own[g][j];
+            cb.y_next = ysl(a, Gh, e + 1);
+            int rc = adj_rhs_fwd(c, g, ysl(a, Gh, e), rslice(c, Gh, a.recv, k - 1), a.ring[0], cb);
             if (rc) return rc;
             std::rotate(a.ring, a.ring + 1, a.ring + m);   // the new value is the newest
         }
-    }
-    for (int g = 0; g < G; ++g) {
-        const GridHost &Gh = c->G[g];
-        AdjGrid &a = A.G[g];
-        HIPCHK(c, hipMemcpyAsync(a.ys, gstate(a, Gh, a.ys, Gh.rate), nelem(Gh) * 8, hipMemcpyDeviceToDevice, c->st));
     }
     return MR_OK;
 }
@@ -1807,12 +1843,12 @@ int adj_macro_rev(mr_ctx *c, int n, int nmacro, double jscale)
             const int e = k / (c->rmax / Gh.rate);
             // undo the push: the newest slot's adjoint is the new value's
             std::rotate(a.lam_ring, a.lam_ring + m - 1, a.lam_ring + m);
-            int rc = adj_rhs_rev(c, g, gstate(a, Gh, a.ys, e), rslice(c, Gh, a.recv, k - 1), a.lam_ring[0],
+            int rc = adj_rhs_rev(c, g, ysl(a, Gh, e), rslice(c, Gh, a.recv, k - 1), a.lam_ring[0],
                                  rslice(c, Gh, a.lam_recv, k - 1), a.lam_y);
             if (rc) return rc;
             HIPCHK(c, hipMemsetAsync(a.lam_ring[0], 0, nelem(Gh) * 8, c->st));
             if (g == A.og && jscale != 0.0)
-                HIPCHK(c, mrk::launch_obj_adj(adj_obj(c), gstate(a, Gh, a.ys, e), Gh.npts,
+                HIPCHK(c, mrk::launch_obj_adj(adj_obj(c), ysl(a, Gh, e), Gh.npts,
                                               jscale * adj_tau(c, n * Gh.rate + e, nmacro), a.lam_y, c->st));
         }
         for (int li = (int)c->links.size() - 1; li >= 0; --li) {
@@ -1824,7 +1860,7 @@ int adj_macro_rev(mr_ctx *c, int n, int nmacro, double jscale)
             const double *lr = rslice(c, c->G[L.rg], A.G[L.rg].lam_recv, k - 1);
             int rc;
             if (!jp) {
-                rc = adj_donor_rev(c, li, gstate(a, D, a.ys, e), lr, a.lam_y);
+                rc = adj_donor_rev(c, li, ysl(a, D, e), lr, a.lam_y);
                 if (rc) return rc;
                 continue;
             }
@@ -1856,7 +1892,8 @@ int adj_macro_rev(mr_ctx *c, int n, int nmacro, double jscale)
     return MR_OK;
 }
 
-// snapshot slot s <- / -> the MRAB quantities (ys[0], ring)
+// snapshot slot s <- / -> the MRAB quantities (the start state, ring); a
+// restore stages the first own step
 int adj_snap(mr_ctx *c, int s, bool store)
 {
     AdjCtx &A = *c->adj;
@@ -1867,12 +1904,12 @@ int adj_snap(mr_ctx *c, int s, bool store)
         const size_t nb = nelem(Gh) * 8;
         double *base = gstate(a, Gh, a.snap, s * (1 + m));
         for (int j = 0; j <= m; ++j) {
-            double *dev = j == 0 ? a.ys : a.ring[j - 1];
+            double *dev = j == 0 ? ysl(a, Gh, 0) : a.ring[j - 1];
             double *sn = base + (size_t)j * nelem(Gh);
             HIPCHK(c, hipMemcpyAsync(store ? sn : dev, store ? dev : sn, nb, hipMemcpyDeviceToDevice, c->st));
         }
     }
-    return MR_OK;
+    return store ? MR_OK : adj_stage(c);
 }
 
 // minimal forward macrosteps to reverse l macrosteps from a stored start
@@ -1927,6 +1964,7 @@ int adj_reverse(mr_ctx *c, const Sched &S, int a, int b, int sa, int s, int nmac
             if (rc) return rc;
             for (int k = a; k < i; ++k) {
                 if ((rc = adj_macro_fwd(c, k, nmacro, false))) return rc;
+                adj_advance(c);
                 nfwd++;
             }
             if ((rc = adj_macro_fwd(c, i, nmacro, false))) return rc;
@@ -1947,6 +1985,7 @@ int adj_reverse(mr_ctx *c, const Sched &S, int a, int b, int sa, int s, int nmac
     if (rc) return rc;
     for (int k = a; k < a + j; ++k) {
         if ((rc = adj_macro_fwd(c, k, nmacro, false))) return rc;
+        adj_advance(c);
         nfwd++;
     }
     if ((rc = adj_snap(c, slot, true))) return rc;
@@ -1975,9 +2014,12 @@ int adj_run_fwd(mr_ctx *c, const double *const *y0, int nmacro, bool obj)
     int rc = adj_boot_fwd(c);
     if (rc) return rc;
     if (obj && A.og >= 0 && !A.opts.empty())
-        HIPCHK(c, mrk::launch_obj(adj_obj(c), A.G[A.og].ys, c->G[A.og].npts, adj_tau(c, 0, nmacro), A.acc, c->st));
-    for (int n = 0; n < nmacro; ++n)
+        HIPCHK(c, mrk::launch_obj(adj_obj(c), ysl(A.G[A.og], c->G[A.og], 0), c->G[A.og].npts, adj_tau(c, 0, nmacro),
+                                  A.acc, c->st));
+    for (int n = 0; n < nmacro; ++n) {
         if ((rc = adj_macro_fwd(c, n, nmacro, obj && A.og >= 0))) return rc;
+        adj_advance(c);
+    }
     return MR_OK;
 }
 
@@ -2918,7 +2960,8 @@ int mr_adj_forward(mr_ctx *c, int nmacro, const double *const *y0, double *const
     if (yN)
         for (size_t g = 0; g < c->G.size(); ++g)
             if (yN[g])
-                HIPCHK(c, hipMemcpyAsync(yN[g], A.G[g].ys, nelem(c->G[g]) * 8, hipMemcpyDeviceToDevice, c->st));
+                HIPCHK(c, hipMemcpyAsync(yN[g], ysl(A.G[g], c->G[g], 0), nelem(c->G[g]) * 8, hipMemcpyDeviceToDevice,
+                                         c->st));
     double v = 0.0;
     HIPCHK(c, hipMemcpyAsync(&v, A.acc, 8, hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
@@ -2944,13 +2987,15 @@ int mr_adj_gradient(mr_ctx *c, int nmacro, const double *const *y0, const double
     if ((rc = adj_boot_fwd(c))) return rc;
     const bool obj = A.og >= 0;
     if (obj)
-        HIPCHK(c, mrk::launch_obj(adj_obj(c), A.G[A.og].ys, c->G[A.og].npts, adj_tau(c, 0, nmacro), A.acc, c->st));
+        HIPCHK(c, mrk::launch_obj(adj_obj(c), ysl(A.G[A.og], c->G[A.og], 0), c->G[A.og].npts, adj_tau(c, 0, nmacro),
+                                  A.acc, c->st));
     std::fill(A.snap_pos.begin(), A.snap_pos.end(), -1);
     if ((rc = adj_snap(c, 0, true))) return rc;
     A.snap_pos[0] = 0;
     int64_t nf = 0;
     for (int n = 0; n < nmacro; ++n) {
         if ((rc = adj_macro_fwd(c, n, nmacro, obj))) return rc;
+        adj_advance(c);
         nf++;
     }
     // reverse: terminal adjoint, macrosteps under the checkpointing schedule,
@@ -2971,7 +3016,8 @@ int mr_adj_gradient(mr_ctx *c, int nmacro, const double *const *y0, const double
     }
     if ((rc = adj_snap(c, 0, false))) return rc;
     if (obj && jscale != 0.0)
-        HIPCHK(c, mrk::launch_obj_adj(adj_obj(c), A.G[A.og].ys, c->G[A.og].npts, jscale * adj_tau(c, 0, nmacro),
+        HIPCHK(c, mrk::launch_obj_adj(adj_obj(c), ysl(A.G[A.og], c->G[A.og], 0), c->G[A.og].npts,
+                                      jscale * adj_tau(c, 0, nmacro),
                                       A.G[A.og].lam_y, c->st));
     if ((rc = adj_boot_rev(c))) return rc;
     for (int g = 0; g < G; ++g)
