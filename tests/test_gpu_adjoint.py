@@ -246,3 +246,32 @@ def test_autograd_function(torch):
     want = sum(float((gr * b).sum()) for gr, b in zip(grads, base))
     _say("autograd", float(s.grad), want)
     assert float(s.grad) == pytest.approx(want, rel=1e-13)
+
+
+@pytest.mark.parametrize("nmacro", [0, 3])
+def test_adj_terminal_adjoint_without_objective(torch, nmacro):
+    """With no objective the gradient is that of <c, y_N> alone (nmacro = 0:
+    the bootstrap only), against central differences of the forward pass."""
+    from oracle.adjoint import richardson
+    from paper_1805_06607_amd.adjoint import Adjoint
+    from paper_1805_06607_amd.system import System
+    wl = CASES["vortex_box"]()
+    sysg = System(wl)
+    sysg.timestep()
+    adj = Adjoint(sysg, nsnap=2)
+    y0 = _base(wl, 12, amp=0.01)
+    rng = np.random.default_rng(5)
+    cs = [rng.standard_normal(y.shape) for y in y0]
+    J, grads, _ = adj.gradient(nmacro, y0, lamN=cs, jscale=0.0)
+    assert J == 0.0
+    grads = [_np(g) for g in grads]
+    for k, v in enumerate(_dirs(y0, 41, 2)):
+        got = sum(float(np.sum(a * b)) for a, b in zip(grads, v))
+
+        def f(e):
+            _, yN = adj.forward(nmacro, [y + e * d for y, d in zip(y0, v)])
+            return sum(float(np.sum(c * _np(y))) for c, y in zip(cs, yN))
+
+        fd = richardson(f, 1e-4)
+        _say("terminal", nmacro, k, got, fd)
+        assert abs(got - fd) <= 1e-7 * abs(fd)
