@@ -152,6 +152,13 @@ extern const TileShape kTileShapes[NUM_TILE_SHAPES];
 int default_tile_shape(const GridDev &g);
 hipError_t launch_rhs_tile2d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *F,
                              const Combine &cb, int shape, hipStream_t st);
+// the same evaluation with one chunked 2D link's extrapolated donor data
+// (a.m > 0) in extra workgroups of the launch; the link must not read or write
+// anything the evaluation writes; shapes of at least 256 threads only
+bool tile2d_donor_ok(int shape);
+hipError_t launch_rhs_tile2d_donor(const GridDev &g, int sbp, const Phys &ph, const double *q, double *F,
+                                   const Combine &cb, int shape, const DonorLink &a, const DonorBlocks &b,
+                                   hipStream_t st);
 // 3D Cartesian right-hand side on LDS tiles of shape 0..NUM_TILE3D_SHAPES-1:
 // a gradient pass into grad (dim (dim+1) x npts scratch), then flux
 // divergence + SAT + AB update

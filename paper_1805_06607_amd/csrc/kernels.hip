@@ -959,7 +959,9 @@ __global__ void __launch_bounds__(256) k_donor_gather(DonorLink a)
 // stencils read, each value with the same separately rounded products and
 // sums as k_extrap, into LDS; q and the Cartesian viscous fluxes once per
 // distinct donor point into LDS; then each receiver's S entries weighted and
-// added by the same butterfly as k_donor_gather.
+// added by the same butterfly as k_donor_gather.  The first 256 threads do
+// the work; threads past them (a larger workgroup shared with other work)
+// only take part in the barriers.
 template <int DIM, int SBP, int CART, int EXT>
 __device__ __forceinline__ void donor_block_body(const DonorLink &a, const DonorBlocks &b, int ch, int j, double *sh)
 {
@@ -999,7 +1001,7 @@ __device__ __forceinline__ void donor_block_body(const DonorLink &a, const Donor
             for (int r = 0; r < XB; ++r) {
                 const int i = base + r * NT + tid;
                 el[r] = -1;
-                if (i < nc * NV) {
+                if (tid < NT && i < nc * NV) {
                     const int v = i / nc, ii = i - v * nc;
                     el[r] = (int64_t)v * N + b.cpts[c0 + ii];
                     ly[r] = y[el[r]];
@@ -1020,7 +1022,7 @@ __device__ __forceinline__ void donor_block_body(const DonorLink &a, const Donor
                 sQ[(size_t)v * b.maxc + ii] = acc;
             }
         }
-        for (int i = tid; i < nu * KP; i += NT) sP[i] = b.bpos[(size_t)u0 * KP + i];
+        for (int i = tid; tid < NT && i < nu * KP; i += NT) sP[i] = b.bpos[(size_t)u0 * KP + i];
         __syncthreads();
     }
     // EXT: the point's own entry, then its gradient stencil in the order
@@ -1038,7 +1040,7 @@ __device__ __forceinline__ void donor_block_body(const DonorLink &a, const Donor
             for (int v = 0; v < NV; ++v) o[v] = y[v * N + idx];
         }
     };
-    for (int u = tid; u < nu; u += NT) {
+    for (int u = tid; tid < NT && u < nu; u += NT) {
         const int64_t p = b.upts[u0 + u];
         pos = sP + (size_t)u * KP;
         cursor = 0;
@@ -1072,7 +1074,7 @@ __device__ __forceinline__ void donor_block_body(const DonorLink &a, const Donor
     __syncthreads();
     const int kk = tid / a.S, e = tid - kk * a.S;
     const int64_t k = (int64_t)ch * b.rpc + kk;
-    const bool ok = kk < b.rpc && k < a.nrecv;
+    const bool ok = tid < NT && kk < b.rpc && k < a.nrecv;
     double val[RB];
     if (ok) {
         const int64_t ent = k * a.S + e;
@@ -1130,6 +1132,29 @@ __global__ void __launch_bounds__(256) k_donor_blocks(const LinkJob *__restrict_
     const LinkJob &J = jobs[lo];
     if ((int)blockIdx.y >= J.a.nj) return;
     donor_block_body<DIM, SBP, CART, EXT>(J.a, J.b, bx - J.chunk0, blockIdx.y, sh);
+}
+
+// A grid's fused right-hand side and, in the same launch, the donor data of
+// one chunked 2D link that neither reads nor writes anything the evaluation
+// touches (another grid's mid-step data, gathered right after that grid
+// evaluated at the same micro-time): workgroups below ntx * nty take the
+// tiles (XCD-ordered as in k_rhs_tile2d), the rest take (chunk, slot) pairs
+// of the link with the first 256 threads.  One launch less per pair.
+template <int SBP, int CART, int TX_, int TY_, int TM_>
+__global__ void __launch_bounds__(TX_ * TY_ * TM_, 2)
+k_rhs_tile2d_donor(GridDev g, Phys ph, const double *__restrict__ q, double *__restrict__ F, Combine cb, int ntx,
+                   int nty, DonorLink a, DonorBlocks b)
+{
+    static_assert(TX_ * TY_ * TM_ >= 256, "the donor body needs 256 threads");
+    extern __shared__ double sh[];
+    const int ntile = ntx * nty;
+    if ((int)blockIdx.x < ntile) {
+        const int tile = xcd_tile(blockIdx.x, ntile);
+        rhs_tile2d_body<SBP, CART, TX_, TY_, TM_>(g, ph, q, F, cb, (tile % ntx) * TX_, (tile / ntx) * TY_);
+    } else {
+        const int d = (int)blockIdx.x - ntile;
+        donor_block_body<2, SBP, 2, 1>(a, b, d % b.nchunk, d / b.nchunk, sh);
+    }
 }
 
 // extrapolated donor states at the donor-stencil points of mid-step links:
@@ -1376,6 +1401,60 @@ hipError_t launch_rhs_tile2d(const GridDev &g, int sbp, const Phys &ph, const do
     case 5: return tile2d_shape<32, 8, 2>(g, sbp, ph, q, F, cb, st);
     case 6: return tile2d_shape<16, 16, 1>(g, sbp, ph, q, F, cb, st);
     case 7: return tile2d_shape<16, 16, 2>(g, sbp, ph, q, F, cb, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int TX, int TY, int TM>
+static hipError_t tile2d_donor_shape(const GridDev &g, int sbp, const Phys &ph, const double *q, double *F,
+                                     const Combine &cb, const DonorLink &a, const DonorBlocks &b, size_t lds,
+                                     hipStream_t st)
+{
+    if constexpr (TX * TY * TM < 256) {
+        return hipErrorInvalidValue;
+    } else {
+        int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY;
+        dim3 grid(ntx * nty + b.nchunk * a.nj), blk(TX * TY * TM);
+        if (sbp == 21 && g.cartesian)
+            hipLaunchKernelGGL((k_rhs_tile2d_donor<21, 1, TX, TY, TM>), grid, blk, lds, st, g, ph, q, F, cb, ntx, nty,
+                               a, b);
+        else if (sbp == 21)
+            hipLaunchKernelGGL((k_rhs_tile2d_donor<21, 0, TX, TY, TM>), grid, blk, lds, st, g, ph, q, F, cb, ntx, nty,
+                               a, b);
+        else if (g.cartesian)
+            hipLaunchKernelGGL((k_rhs_tile2d_donor<42, 1, TX, TY, TM>), grid, blk, lds, st, g, ph, q, F, cb, ntx, nty,
+                               a, b);
+        else
+            hipLaunchKernelGGL((k_rhs_tile2d_donor<42, 0, TX, TY, TM>), grid, blk, lds, st, g, ph, q, F, cb, ntx, nty,
+                               a, b);
+        return hipGetLastError();
+    }
+}
+
+bool tile2d_donor_ok(int shape)
+{
+    return shape >= 0 && shape < NUM_TILE_SHAPES && kTileShapes[shape].tx * kTileShapes[shape].ty * kTileShapes[shape].tm >= 256;
+}
+
+hipError_t launch_rhs_tile2d_donor(const GridDev &g, int sbp, const Phys &ph, const double *q, double *F,
+                                   const Combine &cb, int shape, const DonorLink &a, const DonorBlocks &b,
+                                   hipStream_t st)
+{
+    if (g.dim != 2 || a.g.dim != 2 || a.sbp != sbp || !tile2d_donor_ok(shape)) return hipErrorInvalidValue;
+    if (a.nrecv == 0 || a.nj == 0) return launch_rhs_tile2d(g, sbp, ph, q, F, cb, shape, st);
+    if (a.S < 1 || a.S > 64 || (a.S & (a.S - 1)) || b.rpc * a.S > 256 || a.nj > MAXJ || a.m < 1 ||
+        a.m > MAXH || b.nchunk < 1 || (int64_t)b.nchunk * b.rpc < a.nrecv)
+        return hipErrorInvalidValue;
+    const size_t lds = donor_block_lds(2, b.maxu, b.maxc);
+    switch (shape) {
+    case 0: return tile2d_donor_shape<32, 16, 1>(g, sbp, ph, q, F, cb, a, b, lds, st);
+    case 1: return tile2d_donor_shape<16, 8, 1>(g, sbp, ph, q, F, cb, a, b, lds, st);
+    case 2: return tile2d_donor_shape<16, 8, 2>(g, sbp, ph, q, F, cb, a, b, lds, st);
+    case 3: return tile2d_donor_shape<16, 8, 4>(g, sbp, ph, q, F, cb, a, b, lds, st);
+    case 4: return tile2d_donor_shape<32, 8, 1>(g, sbp, ph, q, F, cb, a, b, lds, st);
+    case 5: return tile2d_donor_shape<32, 8, 2>(g, sbp, ph, q, F, cb, a, b, lds, st);
+    case 6: return tile2d_donor_shape<16, 16, 1>(g, sbp, ph, q, F, cb, a, b, lds, st);
+    case 7: return tile2d_donor_shape<16, 16, 2>(g, sbp, ph, q, F, cb, a, b, lds, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -144,6 +144,7 @@ struct mr_ctx {
     std::vector<int> tgrid_of;                // grid of each timed launch
     bool two_pass = false;    // 2D: use the two-kernel (gradient pass) right-hand side
     bool donor_blocks = true; // one-launch donor data for links whose chunks fit one workgroup
+    bool ride_donors = true;  // one stream: mid-step donor data in the next same-time 2D evaluation's launch
     int tile3d = 1;           // 3D passes: LDS tile shape (mrk::kTile3dShapes), -1 the per-point kernels
     int period = 1;                            // macrosteps after which every pointer repeats
     int64_t version = 0;                       // bumped when a batch's launch plan must be rebuilt
@@ -669,6 +670,66 @@ int links_current2(mr_ctx *c, const std::vector<const Link *> &ls, int k)
     return MR_OK;
 }
 
+// a donor link's data launched inside another grid's right-hand side
+struct Rider {
+    mrk::DonorLink a;
+    mrk::DonorBlocks b;
+};
+
+// the mid-step donor data of link L gathered right after its donor grid
+// evaluated at micro-time k: one slot per later micro-time k' (receiver rows
+// of k' into kps) before the donor's next step at which the receiving grid
+// evaluates; from the extrapolant (chunked links) or the extrapolated
+// buffers
+void future_link(mr_ctx *c, const Link &L, int k, mrk::DonorLink &a, int *kps)
+{
+    const int d = L.dg;
+    const GridHost &D = c->G[d];
+    const GridHost &R = c->G[L.rg];
+    const int per_d = c->rmax / D.rate, per_g = c->rmax / R.rate, m = c->P.hist_len;
+    const bool blk = use_blocks(c, L);
+    a = link_base(c, L);
+    a.nj = 0;
+    if (blk) {
+        a.m = m;
+        for (int j = 0; j < m; ++j) a.hist[j] = slot(c, D, j);
+    }
+    for (int jp = 1; jp < per_d; ++jp) {
+        int kp = k + jp > c->rmax ? k + jp - c->rmax : k + jp;
+        if (kp % per_g) continue;
+        kps[a.nj] = kp;
+        if (blk) {
+            a.ys[a.nj] = D.y[D.cur];
+            for (int j = 0; j < m; ++j) a.beta[a.nj][j] = c->beta[d][jp][j];
+        } else {
+            a.ys[a.nj] = D.ext[jp - 1];
+        }
+        a.out[a.nj] = recv_slice(c, R, kp);
+        a.nj++;
+    }
+}
+
+// the mid-step donor data of grid d (which just evaluated at micro-time k)
+// when it is exactly one chunked 2D link with slots to fill, so that it can
+// ride in the launch of another grid's fused right-hand side
+bool future_rider(mr_ctx *c, int d, int k, Rider &r)
+{
+    const GridHost &D = c->G[d];
+    if (D.dim != 2 || c->rmax / D.rate == 1 || D.closure.empty()) return false;
+    int n = 0;
+    for (const Link &L : c->links) {
+        if (L.dg != d) continue;
+        mrk::DonorLink a;
+        int kps[mrk::MAXJ];
+        future_link(c, L, k, a, kps);
+        if (!a.nj) continue;
+        if (!use_blocks(c, L) || ++n > 1) return false;
+        r.a = a;
+        r.b = link_blocks(L);
+    }
+    return n == 1;
+}
+
 // right after donor grid d evaluated at micro-time k: its extrapolant is
 // fixed until its next step, so the donor data of every later micro-time
 // k' < k + per_d at which a receiving grid evaluates is gathered now:
@@ -709,34 +770,16 @@ int donor_future(mr_ctx *c, int d, int k, int si)
     }
     for (const Link &L : c->links) {
         if (L.dg != d) continue;
-        const GridHost &R = c->G[L.rg];
-        int per_g = c->rmax / R.rate;
-        const bool blk = use_blocks(c, L);
-        mrk::DonorLink a = link_base(c, L);
-        a.nj = 0;
-        if (blk) {
-            a.m = x.m;
-            for (int j = 0; j < x.m; ++j) a.hist[j] = x.hist[j];
-        }
+        mrk::DonorLink a;
         int kps[mrk::MAXJ];
-        for (int jp = 1; jp < per_d; ++jp) {
-            int kp = kprime(jp);
-            if (kp % per_g) continue;
-            if (si >= 0) {
-                int rc = ord_need(c, si, ord_rd(c, L.rg, kp));   // rows last read by the receiver at kp
+        future_link(c, L, k, a, kps);
+        if (si >= 0)
+            for (int j = 0; j < a.nj; ++j) {
+                int rc = ord_need(c, si, ord_rd(c, L.rg, kps[j]));   // rows last read by the receiver
                 if (rc) return rc;
             }
-            kps[a.nj] = kp;
-            if (blk) {
-                a.ys[a.nj] = D.y[D.cur];
-                for (int j = 0; j < x.m; ++j) a.beta[a.nj][j] = c->beta[d][jp][j];
-            } else {
-                a.ys[a.nj] = D.ext[jp - 1];
-            }
-            a.out[a.nj] = recv_slice(c, R, kp);
-            a.nj++;
-        }
         if (!a.nj) continue;
+        const bool blk = use_blocks(c, L);
         if (blk)
             HIPCHK(c, mrk::launch_donor_block(a, link_blocks(L), st));
         else
@@ -749,8 +792,13 @@ int donor_future(mr_ctx *c, int d, int k, int si)
     return ord_mark(c, si);
 }
 
-// right-hand side of one grid from state q into F (+ optional fused combine)
-int grid_rhs(mr_ctx *c, int gi, const double *q, double *F, const mrk::Combine &cb, bool timed, int k, int si)
+int shape_of(const GridHost &g);
+
+// right-hand side of one grid from state q into F (+ optional fused combine,
+// + optional rider: a donor link's data launched in the same kernel)
+
+int grid_rhs(mr_ctx *c, int gi, const double *q, double *F, const mrk::Combine &cb, bool timed, int k, int si,
+             const Rider *ride = nullptr)
 {
     hipStream_t st = sst(c, si);
     if (si >= 0)
@@ -764,7 +812,9 @@ int grid_rhs(mr_ctx *c, int gi, const double *q, double *F, const mrk::Combine &
     dev.recv = recv_slice(c, g, k);
     bool rec = timed && (c->tgrid == gi || c->tgrid == -2) && c->tcount < c->tmax;
     if (rec) HIPCHK(c, hipEventRecord(c->ev[2 * c->tcount], st));
-    if (g.dim == 2 && !c->two_pass) {
+    if (ride) {
+        HIPCHK(c, mrk::launch_rhs_tile2d_donor(dev, c->P.sbp, c->ph, q, F, cb, shape_of(g), ride->a, ride->b, st));
+    } else if (g.dim == 2 && !c->two_pass) {
         int shape = g.tile >= 0 ? g.tile : mrk::default_tile_shape(dev);
         HIPCHK(c, mrk::launch_rhs_tile2d(dev, c->P.sbp, c->ph, q, F, cb, shape, st));
     } else if (g.dim == 3 && c->tile3d >= 0) {
@@ -952,6 +1002,13 @@ int run_macrosteps(mr_ctx *c, int nsteps, bool ms, hipStream_t origin, const EvS
                 int rc = links_current2(c, pair, k);
                 if (rc) return rc;
             }
+            // (one stream) a grid's mid-step donor data reads only that
+            // grid's state and history and writes receiver rows of other
+            // micro-times than k, so it rides in the launch of the next grid
+            // evaluated at k when both fit the combined kernel
+            bool rode[mrk::MAXG] = {};
+            int pend = -1;
+            Rider rider;
             for (int g = 0; g < G; ++g) {
                 if (!ends[g]) continue;
                 GridHost &Gh = c->G[g];
@@ -961,12 +1018,19 @@ int run_macrosteps(mr_ctx *c, int nsteps, bool ms, hipStream_t origin, const EvS
                 for (int j = 0; j < m; ++j) cb.c[j] = c->c_own[g][j];
                 cb.y_next = Gh.y[1 - Gh.cur];
                 double *Fnew = slot(c, Gh, 0);      // the oldest slot is overwritten
-                int rc = grid_rhs(c, g, Gh.y[Gh.cur], Fnew, cb, true, k, gsi(g));
+                const bool timing = (c->tgrid == g || c->tgrid == -2) && c->tcount < c->tmax;
+                const bool take = pend >= 0 && fused2d(c, Gh) && mrk::tile2d_donor_ok(shape_of(Gh)) && !timing;
+                int rc = grid_rhs(c, g, Gh.y[Gh.cur], Fnew, cb, true, k, gsi(g), take ? &rider : nullptr);
                 if (rc) return rc;
+                if (take) {
+                    rode[pend] = true;
+                    pend = -1;
+                }
                 Gh.head = (Gh.head + 1) % m;
+                if (!ms && c->ride_donors && pend < 0 && future_rider(c, g, k, rider)) pend = g;
             }
             for (int g = 0; g < G; ++g) {
-                if (!ends[g]) continue;
+                if (!ends[g] || rode[g]) continue;
                 int rc = donor_future(c, g, k, gsi(g));
                 if (rc) return rc;
             }
@@ -2646,6 +2710,9 @@ int mr_set_option(mr_ctx *c, const char *name, int64_t value)
         if (value < -1 || value >= mrk::NUM_TILE3D_SHAPES)
             return fail(c, MR_ERR_ARG, "rhs_tile3d must be -1 .. %d", mrk::NUM_TILE3D_SHAPES - 1);
         c->tile3d = (int)value;
+    } else if (!strcmp(name, "ride_donors")) {
+        if (value != 0 && value != 1) return fail(c, MR_ERR_ARG, "ride_donors must be 0 or 1");
+        c->ride_donors = value == 1;
     } else if (!strcmp(name, "graph")) {
         if (value != 0 && value != 1) return fail(c, MR_ERR_ARG, "graph must be 0 or 1");
         if (value) return fail(c, MR_ERR_UNSUPPORTED, "graph replay of macrosteps is switched off");

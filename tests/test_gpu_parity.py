@@ -272,6 +272,39 @@ def test_multi_stream_bitwise(torch, case):
         assert t[0] == t[1], t
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", ["vortex_box", "cylinder_small"])
+@pytest.mark.parametrize("host_shape", [None, 1])
+def test_ride_donors_bitwise(torch, case, host_shape):
+    """A slow grid's mid-step donor data launched inside the next same-time
+    grid's right-hand side (one launch less) gives the same bits as its own
+    launch.  host_shape 1 (16 x 8 tiles, 128 threads) is too small to carry
+    it, so that run checks the fallback to separate launches."""
+    from paper_1805_06607_amd.system import System
+    systems = {}
+    for name, ride in (("separate", 0), ("riding", 1)):
+        wl = CASES[case]()
+        s = System(wl)
+        s.set_option("multi_stream", 0)
+        s.set_option("ride_donors", ride)
+        if host_shape is not None:
+            s.set_tile_shape(1, host_shape)
+        s.timestep()
+        s.start(0.0)
+        systems[name] = s
+    ng = len(wl.grids)
+    m = wl.params["hist_len"]
+    for n in (1, 3, 8):
+        snap = {}
+        for name, s in systems.items():
+            s.macrostep(n)
+            torch.cuda.synchronize()
+            snap[name] = [s.state(g).clone() for g in range(ng)] + \
+                [s.history(g, j).clone() for g in range(ng) for j in range(m)]
+        for a, b in zip(snap["separate"], snap["riding"]):
+            assert torch.equal(a, b), (case, host_shape, n)
+
+
 @pytest.mark.skip(reason="graph replay of captured macrosteps is switched off: both runs of the "
                          "capture path ended the process with a segmentation fault inside the HIP "
                          "runtime; cause not found")
