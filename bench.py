@@ -301,9 +301,21 @@ def run_adjoint(args):
     print(json.dumps(line), flush=True)
 
 
+TILE3D = (16, 8, 4)   # the 3D passes' default LDS tile (option rhs_tile3d = 1)
+
+
 def kernel_names(sysg, wl):
-    """Kernel instantiation of each grid's fused 2D right-hand side."""
+    """Key of each grid's right-hand-side launches in the counter summary:
+    the fused 2D kernel's instantiation, or for 3D the gradient + flux pass
+    pair by its launch size (threads)."""
     names = []
+    if wl.dim == 3:
+        for gr in wl.grids:
+            threads = 1
+            for n, t in zip(gr.n, TILE3D):
+                threads *= -(-n // t) * t
+            names.append(f"tile3d_pair grid={threads}")
+        return names
     for g, gr in enumerate(wl.grids):
         shape, tx, ty, tm = sysg.tile_shape(g)
         if shape < 0:
@@ -332,6 +344,9 @@ def stored_traffic():
             elif ln.startswith("k_") and "bytes_per_launch=" in ln:
                 name, val = ln.rsplit("bytes_per_launch=", 1)
                 out[name.split(" grid=")[0].strip()] = float(val)
+            elif ln.startswith("tile3d_pair") and "bytes_per_launch=" in ln:
+                name, val = ln.rsplit("bytes_per_launch=", 1)
+                out[name.strip()] = float(val)
     return out if ok else {}
 
 
@@ -352,7 +367,7 @@ def roofline(sysg, wl, n_act, what):
     the timed region: algorithmic bytes (bytes_per_point x active points per
     launch) / summed launch duration, and per grid."""
     per_grid, tb, tt, tn = [], 0.0, 0.0, 0
-    names = kernel_names(sysg, wl) if wl.dim == 2 else [None] * len(wl.grids)
+    names = kernel_names(sysg, wl)
     traffic = stored_traffic()
     tr_bytes, tr_ok = 0.0, True
     for g in range(len(wl.grids)):

@@ -251,6 +251,20 @@ int mr_kernel_time(mr_ctx *ctx, double *total_ms, int *count);
  *                        the halo slabs are evaluated per direction), or -1
  *                        for the point-wise kernels (default 1).  Same
  *                        formulas; results agree to rounding.
+ *  "tile3d_slab"         3D tiled passes: the order in which the launch
+ *                        takes its tiles.  n > 0: slabs of n tile rows along
+ *                        y, each slab taken plane by plane along z, so a
+ *                        tile's z neighbours are n tile rows away and their
+ *                        halo data is still in the cache; 0: plain x, y, z
+ *                        order (default 3).  Each output is computed alone, so
+ *                        results are bitwise the same for every value.
+ *  "ride_donors"         1: with one stream, the mid-step donor data of a
+ *                        slower 2D grid (one chunked link) is produced inside
+ *                        the launch of the next grid evaluated at the same
+ *                        micro-time, in workgroups of its own, when that
+ *                        grid's 2D tile has at least 256 threads; it reads
+ *                        and writes nothing that evaluation touches.  0: a
+ *                        launch of its own (default 1).  Bitwise the same.
  *  "graph"               reserved: 1 (replaying captured HIP graphs of whole
  *                        macrostep periods) is switched off and returns
  *                        MR_ERR_UNSUPPORTED; 0 is accepted.

@@ -165,8 +165,10 @@ hipError_t launch_rhs_tile2d_donor(const GridDev &g, int sbp, const Phys &ph, co
 struct TileShape3 { int tx, ty, tz; };
 constexpr int NUM_TILE3D_SHAPES = 4;
 extern const TileShape3 kTile3dShapes[NUM_TILE3D_SHAPES];
+// slab: tiles are taken in slabs of that many tile rows along y, z planes
+// within a slab (<= 0 or >= the tile rows: the plain x, y, z order)
 hipError_t launch_rhs_tile3d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *grad,
-                             double *F, const Combine &cb, int shape, hipStream_t st);
+                             double *F, const Combine &cb, int shape, int slab, hipStream_t st);
 hipError_t launch_combine(int64_t n, const double *y, const Combine &cb, hipStream_t st);
 hipError_t launch_axpy(int64_t n, const double *y, double a, const double *x, double *out, hipStream_t st);
 hipError_t launch_rk3_final(int64_t n, const double *y, double a, const double *k1, const double *k3,

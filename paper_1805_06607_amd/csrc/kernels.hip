@@ -300,17 +300,37 @@ __device__ __forceinline__ void fluxes3(const GridDev &g, const Phys &ph, const 
     for (int m = 0; m < 3; ++m) out[m] = fhat_at<3, 1>(g, ph, q, grad, m, idx);
 }
 
+// tile coordinates (in tiles) of the tile-th tile of a 3D launch: the tile
+// rows are cut into slabs of sy rows along y (the last slab may be shorter);
+// slab by slab, the tiles are taken in planes of constant z, each plane row by
+// row, x fastest.  A tile's z neighbours then lie ntx * sy tiles away in this
+// order (sy = nty: the plain x, y, z order).
+__device__ __forceinline__ void tile3_origin(int tile, int ntx, int nty, int ntz, int sy, int *t)
+{
+    const int per = ntx * sy * ntz;   // tiles of a full slab
+    const int s = tile / per, rem = tile - s * per;
+    const int h = min(sy, nty - s * sy);
+    const int z = rem / (ntx * h), r2 = rem - z * (ntx * h);
+    t[0] = r2 % ntx;
+    t[1] = s * sy + r2 / ntx;
+    t[2] = z;
+}
+
 // 3D Cartesian gradient pass on tiles: grad[(a*3+j)*N + p] = d(u, v, w, T)_a / dx_j
 // (zero at holes), the formulas of k_grad
 template <int SBP, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(TX * TY * TZ) k_grad_tile3d(GridDev g, double gm1, const double *__restrict__ q,
-                                                              double *__restrict__ grad, int ntx, int nty, int ntz)
+                                                              double *__restrict__ grad, int ntx, int nty, int ntz,
+                                                              int sy)
 {
     constexpr int R = SBP == 21 ? 1 : 3;
     using C = Tile3<TX, TY, TZ, R>;
     __shared__ double sW[4][C::RMAX];
-    const int tile = xcd_tile(blockIdx.x, ntx * nty * ntz);
-    const int t0[3] = {(tile % ntx) * TX, ((tile / ntx) % nty) * TY, (tile / (ntx * nty)) * TZ};
+    int t0[3];
+    tile3_origin(xcd_tile(blockIdx.x, ntx * nty * ntz), ntx, nty, ntz, sy, t0);
+    t0[0] *= TX;
+    t0[1] *= TY;
+    t0[2] *= TZ;
     const int tid = threadIdx.x;
     const int lc[3] = {tid % TX, (tid / TX) % TY, tid / (TX * TY)};
     const int64_t N = g.npts;
@@ -394,13 +414,16 @@ template <int SBP, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(TX * TY * TZ) k_rhs_tile3d(GridDev g, Phys ph, const double *__restrict__ q,
                                                              const double *__restrict__ grad,
                                                              double *__restrict__ F, Combine cb, int ntx, int nty,
-                                                             int ntz)
+                                                             int ntz, int sy)
 {
     constexpr int NV = 5, R = SBP == 21 ? 1 : 3;
     using C = Tile3<TX, TY, TZ, R>;
     __shared__ double sF[NV][C::RMAX];
-    const int tile = xcd_tile(blockIdx.x, ntx * nty * ntz);
-    const int t0[3] = {(tile % ntx) * TX, ((tile / ntx) % nty) * TY, (tile / (ntx * nty)) * TZ};
+    int t0[3];
+    tile3_origin(xcd_tile(blockIdx.x, ntx * nty * ntz), ntx, nty, ntz, sy, t0);
+    t0[0] *= TX;
+    t0[1] *= TY;
+    t0[2] *= TZ;
     const int tid = threadIdx.x;
     const int lc[3] = {tid % TX, (tid / TX) % TY, tid / (TX * TY)};
     const int64_t N = g.npts;
@@ -1466,31 +1489,34 @@ const TileShape3 kTile3dShapes[NUM_TILE3D_SHAPES] = {{8, 8, 8}, {16, 8, 4}, {32,
 
 template <int TX, int TY, int TZ>
 static hipError_t tile3d_shape(const GridDev &g, int sbp, const Phys &ph, const double *q, double *grad,
-                               double *F, const Combine &cb, hipStream_t st)
+                               double *F, const Combine &cb, int slab, hipStream_t st)
 {
     const int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY, ntz = (g.n[2] + TZ - 1) / TZ;
+    const int sy = slab > 0 && slab < nty ? slab : nty;
     const dim3 grid((unsigned)(ntx * nty * ntz)), block(TX * TY * TZ);
     const double gm1 = ph.gamma - 1.0;
     double *gw = grad;
     if (sbp == 21) {
-        hipLaunchKernelGGL((k_grad_tile3d<21, TX, TY, TZ>), grid, block, 0, st, g, gm1, q, gw, ntx, nty, ntz);
-        hipLaunchKernelGGL((k_rhs_tile3d<21, TX, TY, TZ>), grid, block, 0, st, g, ph, q, grad, F, cb, ntx, nty, ntz);
+        hipLaunchKernelGGL((k_grad_tile3d<21, TX, TY, TZ>), grid, block, 0, st, g, gm1, q, gw, ntx, nty, ntz, sy);
+        hipLaunchKernelGGL((k_rhs_tile3d<21, TX, TY, TZ>), grid, block, 0, st, g, ph, q, grad, F, cb, ntx, nty, ntz,
+                           sy);
     } else {
-        hipLaunchKernelGGL((k_grad_tile3d<42, TX, TY, TZ>), grid, block, 0, st, g, gm1, q, gw, ntx, nty, ntz);
-        hipLaunchKernelGGL((k_rhs_tile3d<42, TX, TY, TZ>), grid, block, 0, st, g, ph, q, grad, F, cb, ntx, nty, ntz);
+        hipLaunchKernelGGL((k_grad_tile3d<42, TX, TY, TZ>), grid, block, 0, st, g, gm1, q, gw, ntx, nty, ntz, sy);
+        hipLaunchKernelGGL((k_rhs_tile3d<42, TX, TY, TZ>), grid, block, 0, st, g, ph, q, grad, F, cb, ntx, nty, ntz,
+                           sy);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_rhs_tile3d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *grad,
-                             double *F, const Combine &cb, int shape, hipStream_t st)
+                             double *F, const Combine &cb, int shape, int slab, hipStream_t st)
 {
     if (g.dim != 3 || !g.cartesian || (sbp != 21 && sbp != 42)) return hipErrorInvalidValue;
     switch (shape) {
-    case 0: return tile3d_shape<8, 8, 8>(g, sbp, ph, q, grad, F, cb, st);
-    case 1: return tile3d_shape<16, 8, 4>(g, sbp, ph, q, grad, F, cb, st);
-    case 2: return tile3d_shape<32, 4, 4>(g, sbp, ph, q, grad, F, cb, st);
-    case 3: return tile3d_shape<16, 4, 4>(g, sbp, ph, q, grad, F, cb, st);
+    case 0: return tile3d_shape<8, 8, 8>(g, sbp, ph, q, grad, F, cb, slab, st);
+    case 1: return tile3d_shape<16, 8, 4>(g, sbp, ph, q, grad, F, cb, slab, st);
+    case 2: return tile3d_shape<32, 4, 4>(g, sbp, ph, q, grad, F, cb, slab, st);
+    case 3: return tile3d_shape<16, 4, 4>(g, sbp, ph, q, grad, F, cb, slab, st);
     default: return hipErrorInvalidValue;
     }
 }

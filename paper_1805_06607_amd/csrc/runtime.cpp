@@ -146,6 +146,7 @@ struct mr_ctx {
     bool donor_blocks = true; // one-launch donor data for links whose chunks fit one workgroup
     bool ride_donors = true;  // one stream: mid-step donor data in the next same-time 2D evaluation's launch
     int tile3d = 1;           // 3D passes: LDS tile shape (mrk::kTile3dShapes), -1 the per-point kernels
+    int slab3d = 3;           // 3D passes: tile rows per slab of the tile order (0: plain x, y, z order)
     int period = 1;                            // macrosteps after which every pointer repeats
     int64_t version = 0;                       // bumped when a batch's launch plan must be rebuilt
     // macrosteps: one stream per grid, ordered by events (Order); -1: when
@@ -818,7 +819,7 @@ int grid_rhs(mr_ctx *c, int gi, const double *q, double *F, const mrk::Combine &
         int shape = g.tile >= 0 ? g.tile : mrk::default_tile_shape(dev);
         HIPCHK(c, mrk::launch_rhs_tile2d(dev, c->P.sbp, c->ph, q, F, cb, shape, st));
     } else if (g.dim == 3 && c->tile3d >= 0) {
-        HIPCHK(c, mrk::launch_rhs_tile3d(dev, c->P.sbp, c->ph, q, g.grad, F, cb, c->tile3d, st));
+        HIPCHK(c, mrk::launch_rhs_tile3d(dev, c->P.sbp, c->ph, q, g.grad, F, cb, c->tile3d, c->slab3d, st));
     } else {
         HIPCHK(c, mrk::launch_grad(dev, c->P.sbp, c->P.gamma - 1.0, q, g.grad, st));
         HIPCHK(c, mrk::launch_rhs(dev, c->grids_d + gi, c->P.sbp, c->ph, q, g.grad, F, cb, st));
@@ -2706,6 +2707,9 @@ int mr_set_option(mr_ctx *c, const char *name, int64_t value)
     } else if (!strcmp(name, "donor_blocks")) {
         if (value != 0 && value != 1) return fail(c, MR_ERR_ARG, "donor_blocks must be 0 or 1");
         c->donor_blocks = value != 0;
+    } else if (!strcmp(name, "tile3d_slab")) {
+        if (value < 0 || value > 1024) return fail(c, MR_ERR_ARG, "tile3d_slab must be 0 .. 1024");
+        c->slab3d = (int)value;
     } else if (!strcmp(name, "rhs_tile3d")) {
         if (value < -1 || value >= mrk::NUM_TILE3D_SHAPES)
             return fail(c, MR_ERR_ARG, "rhs_tile3d must be -1 .. %d", mrk::NUM_TILE3D_SHAPES - 1);

@@ -106,3 +106,25 @@ def test_multi_stream_bitwise_3d(torch):
         outs.append([s.state(g).clone() for g in range(len(wl.grids))])
     for g, (a, b) in enumerate(zip(*outs)):
         assert torch.equal(a, b), g
+
+
+@pytest.mark.parametrize("tile3d", [1, 2])
+def test_tile3d_slab_bitwise(torch, tile3d):
+    """The order in which the 3D passes take their tiles (slabs of 1, 4 or 5
+    tile rows, the last one shorter, or the plain order) changes no bit of
+    the states after 6 macrosteps."""
+    from paper_1805_06607_amd.system import System
+    outs = []
+    for slab in (0, 1, 4, 5):
+        wl = small()
+        s = System(wl)
+        s.set_option("multi_stream", 0)
+        s.set_option("rhs_tile3d", tile3d)
+        s.set_option("tile3d_slab", slab)
+        s.timestep()
+        s.start(0.0)
+        s.macrostep(6)
+        outs.append([s.state(g).clone() for g in range(len(wl.grids))])
+    for o in outs[1:]:
+        for g, (a, b) in enumerate(zip(outs[0], o)):
+            assert torch.equal(a, b), (tile3d, g)
