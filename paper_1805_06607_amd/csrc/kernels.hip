@@ -909,39 +909,53 @@ __global__ void __launch_bounds__(256) k_donor_vals(DonorLink a)
 {
     constexpr int NV = DIM + 2;
     constexpr int RB = NV + DIM * (NV - 1);
-    int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = (int)(lane / a.nu);
-    if (j >= a.nj) return;
-    const int64_t u = lane - (int64_t)j * a.nu;
-    const int64_t p = a.upts[u];
-    const int64_t N = a.g.npts;
-    const double *y = nullptr;
+    __shared__ double sv[256 * RB];
+    const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nl = a.nu * a.nj;               // lanes with a row to write
+    const int wl = threadIdx.x & 63;
+    double *ws = sv + (threadIdx.x - wl) * RB;    // this wave's 64 rows
+    if (lane < nl) {
+        const int j = (int)(lane / a.nu);
+        const int64_t u = lane - (int64_t)j * a.nu;
+        const int64_t p = a.upts[u];
+        const int64_t N = a.g.npts;
+        const double *y = nullptr;
 #pragma unroll
-    for (int jj = 0; jj < MAXJ; ++jj)
-        if (jj == j) y = a.ys[jj];
-    auto qload = [&](int64_t idx, double *o) {
+        for (int jj = 0; jj < MAXJ; ++jj)
+            if (jj == j) y = a.ys[jj];
+        auto qload = [&](int64_t idx, double *o) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) o[v] = y[v * N + idx];
-    };
-    double qp[NV];
-    qload(p, qp);
-    int ic[3];
-    coords(a.g, p, ic);
-    double gr[DIM + 1][DIM];
-    gradient<DIM, SBP, CART>(a.g, p, ic, a.ph.gamma - 1.0, qload, gr);
-    double u_[DIM];
-    double ri = 1.0 / qp[0];
+            for (int v = 0; v < NV; ++v) o[v] = y[v * N + idx];
+        };
+        double qp[NV];
+        qload(p, qp);
+        int ic[3];
+        coords(a.g, p, ic);
+        double gr[DIM + 1][DIM];
+        gradient<DIM, SBP, CART>(a.g, p, ic, a.ph.gamma - 1.0, qload, gr);
+        double u_[DIM];
+        double ri = 1.0 / qp[0];
 #pragma unroll
-    for (int i = 0; i < DIM; ++i) u_[i] = qp[1 + i] * ri;
-    double Fv[DIM][DIM + 1];
-    viscous_flux<DIM>(a.ph, u_, gr, Fv);
-    double *o = a.vals + ((int64_t)j * a.nu + u) * RB;
+        for (int i = 0; i < DIM; ++i) u_[i] = qp[1 + i] * ri;
+        double Fv[DIM][DIM + 1];
+        viscous_flux<DIM>(a.ph, u_, gr, Fv);
+        double *o = ws + wl * RB;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) o[v] = qp[v];
+        for (int v = 0; v < NV; ++v) o[v] = qp[v];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d)
+        for (int d = 0; d < DIM; ++d)
 #pragma unroll
-        for (int v = 1; v < NV; ++v) o[NV + d * (NV - 1) + (v - 1)] = Fv[d][v - 1];
+            for (int v = 1; v < NV; ++v) o[NV + d * (NV - 1) + (v - 1)] = Fv[d][v - 1];
+    }
+    __syncthreads();
+    // lane (j, u) owns row j * nu + u of a.vals, so the wave's rows are one
+    // contiguous block: written with consecutive lanes on consecutive doubles
+    const int64_t lane0 = lane - wl;
+#pragma unroll
+    for (int c = 0; c < RB; ++c) {
+        const int f = c * 64 + wl;
+        if (lane0 + f / RB < nl) a.vals[lane0 * RB + f] = ws[f];
+    }
 }
 
 // Receiver rows: Lagrange-weighted sum of the donor values; one lane per

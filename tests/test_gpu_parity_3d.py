@@ -128,3 +128,80 @@ def test_tile3d_slab_bitwise(torch, tile3d):
     for o in outs[1:]:
         for g, (a, b) in enumerate(zip(outs[0], o)):
             assert torch.equal(a, b), (tile3d, g)
+
+
+def _near_boundary(ib, n, reach=3):
+    """Active points (flat, x fastest) with an inactive point or a grid edge
+    within `reach` points along some axis: where closure rows and SAT terms
+    act."""
+    act = np.asarray(ib).astype(bool).reshape(n[2], n[1], n[0])
+    near = np.zeros_like(act)
+    for ax in range(3):
+        for s in range(1, reach + 1):
+            near |= np.roll(~act, s, axis=ax) | np.roll(~act, -s, axis=ax)
+        idx = [slice(None)] * 3
+        idx[ax] = slice(0, reach)
+        near[tuple(idx)] = True
+        idx[ax] = slice(act.shape[ax] - reach, None)
+        near[tuple(idx)] = True
+    return np.flatnonzero((near & act).ravel())
+
+
+@pytest.fixture(scope="module")
+def full3d(torch):
+    from paper_1805_06607_amd.system import System
+    wl = workloads.tgv3d()
+    _say("full-size 3D setup", [g.n for g in wl.grids])
+    return wl, System(wl)
+
+
+def test_full_size_sampled_3d(torch, full3d):
+    """Full-size 3D case (192^3 background, two 96^3 patches, 64^3 inner
+    patch) with the launch plan the bench times (16 x 8 x 4 tiles in slab
+    order): every receiver row, and the right-hand side at 3000 sampled
+    active points per grid (half of them within three points of a hole, an
+    interface face or a grid edge), against the oracle evaluated point by
+    point on the same seeded state."""
+    from oracle import OracleSystem
+    wl, sysg = full3d
+    states = workloads.random_state_like(wl, seed=21, amp=0.02)
+    got = [_np(t) for t in sysg.rhs(states)]
+    gotr = [_np(sysg.receiver_data(g, states)) for g in range(len(wl.grids))]
+    _say("full-size 3D: oracle setup")
+    orc = OracleSystem(wl)
+    rng = np.random.default_rng(5)
+    for g, gr in enumerate(wl.grids):
+        recv = orc.receiver_data(g, states)
+        e = rel_l2(gotr[g].T, recv.T)
+        _say("full 3d receiver data", g, recv.shape, e)
+        assert np.all(e <= 1e-13), (g, e)
+        act = np.flatnonzero(orc.grids[g].iblank)
+        nb = _near_boundary(orc.grids[g].iblank, gr.n)
+        pts = np.unique(np.concatenate([rng.choice(act, 1500, replace=False),
+                                        rng.choice(nb, min(1500, nb.size), replace=False)]))
+        want = orc.rhs_points(g, states[g], recv, pts)
+        e = rel_l2(got[g][:, pts], want.T)
+        _say("full 3d rhs sampled", g, pts.size, e)
+        assert np.all(e <= 1e-12), (g, e)
+
+
+def test_full_size_freestream_3d(torch, full3d):
+    """Uniform flow is a steady state of the discretisation (free-stream
+    preservation): the RK bootstrap and 3 MRAB macrosteps of the full-size 3D
+    case, with per-grid streams and the tiled passes as the bench runs them,
+    leave every active point's state unchanged to rounding."""
+    wl, sysg = full3d
+    g0 = wl.params["gamma"]
+    p0 = 1.0 / (g0 * 0.3 * 0.3)
+    u = (0.3, -0.2, 0.1)
+    q = np.array([1.0, u[0], u[1], u[2], p0 / (g0 - 1.0) + 0.5 * sum(c * c for c in u)])
+    uni = [np.repeat(q[:, None], gr.npts, axis=1) for gr in wl.grids]
+    sysg.set_states(uni)
+    sysg.timestep()
+    sysg.start(0.0)
+    sysg.macrostep(3)
+    for g in range(len(wl.grids)):
+        act = np.asarray(sysg.iblanks[g]).astype(bool)
+        d = np.abs(_np(sysg.state(g))[:, act] - q[:, None]).max(axis=1) / np.abs(q)
+        _say("full 3d free stream", g, d)
+        assert np.all(d <= 1e-12), (g, d)
