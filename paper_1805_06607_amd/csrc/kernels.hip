@@ -959,10 +959,18 @@ __global__ void __launch_bounds__(256) k_donor_vals(DonorLink a)
 }
 
 // Receiver rows: Lagrange-weighted sum of the donor values; one lane per
-// (slot, receiver, entry), a fixed butterfly over the S lanes of a receiver.
+// (slot, receiver, entry), summed over the S lanes of a receiver by a
+// transposed butterfly.  At the step of lane offset 2^b every component's
+// partial sum over a block of 2^b lanes meets its partner block's, as in a
+// plain butterfly (so each component is the same tree of additions), but a
+// lane keeps only half of its components (the upper half when bit b of its
+// entry is set) and sends the other half: with RB padded to P components,
+// log2(P) steps leave one component per lane and about P shuffles in all
+// instead of RB per step.
 template <int RB>
 __global__ void __launch_bounds__(256) k_donor_gather(DonorLink a)
 {
+    constexpr int P = RB <= 16 ? 16 : 32;
     int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t per_slot = a.nrecv * a.S;
     const int j = (int)(lane / per_slot);
@@ -977,18 +985,37 @@ __global__ void __launch_bounds__(256) k_donor_gather(DonorLink a)
     const int64_t ent = k * a.S + e;
     const double w = a.w[ent];
     const double *vrow = a.vals + ((int64_t)j * a.nu + a.uid[ent]) * RB;
-    double val[RB];
+    double v[P];
 #pragma unroll
-    for (int t = 0; t < RB; ++t) val[t] = w * vrow[t];
-    for (int off = 1; off < a.S; off <<= 1) {
+    for (int t = 0; t < P; ++t) v[t] = t < RB ? w * vrow[t] : 0.0;
+    int base = 0;       // component held in v[0]
+    int halving = 0;    // halving steps taken
 #pragma unroll
-        for (int t = 0; t < RB; ++t) val[t] += __shfl_xor(val[t], off, 64);
+    for (int b = 0; b < 6; ++b) {
+        const int off = 1 << b;
+        if (off >= a.S) break;
+        const int half = (P >> b) / 2;
+        if (half >= 1) {
+            const bool hi = (e & off) != 0;
+#pragma unroll
+            for (int i = 0; i < half; ++i) {
+                const double send = hi ? v[i] : v[i + half];
+                const double keep = hi ? v[i + half] : v[i];
+                v[i] = keep + __shfl_xor(send, off, 64);
+            }
+            if (hi) base += half;
+            ++halving;
+        } else {
+            v[0] = v[0] + __shfl_xor(v[0], off, 64);
+        }
     }
-    if (e == 0) {
-        double *o = outp + (int64_t)(a.row0 + k) * RB;
+    // lanes that differ only in bits past the halving steps hold the same sums
+    if (e >> halving) return;
+    const int cnt = P >> halving;
+    double *o = outp + (int64_t)(a.row0 + k) * RB;
 #pragma unroll
-        for (int t = 0; t < RB; ++t) o[t] = val[t];
-    }
+    for (int i = 0; i < P; ++i)
+        if (i < cnt && base + i < RB) o[base + i] = v[i];
 }
 
 // Receiver rows of one chunk of receivers for slot j = blockIdx.y in one
