@@ -1023,9 +1023,10 @@ __global__ void __launch_bounds__(256) k_donor_gather(DonorLink a)
 // stencils read, each value with the same separately rounded products and
 // sums as k_extrap, into LDS; q and the Cartesian viscous fluxes once per
 // distinct donor point into LDS; then each receiver's S entries weighted and
-// added by the same butterfly as k_donor_gather.  The first 256 threads do
-// the work; threads past them (a larger workgroup shared with other work)
-// only take part in the barriers.
+// added by a plain butterfly over the S lanes (the same tree of additions,
+// so the same bits, as k_donor_gather's transposed one).  The first 256
+// threads do the work; threads past them (a larger workgroup shared with
+// other work) only take part in the barriers.
 template <int DIM, int SBP, int CART, int EXT>
 __device__ __forceinline__ void donor_block_body(const DonorLink &a, const DonorBlocks &b, int ch, int j, double *sh)
 {
