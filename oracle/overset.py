@@ -21,6 +21,11 @@ follows these readings:
   fractional index lies inside the grid and covers only active points.  The
   stencil base is floor(f) - (W/2 - 1); weights are tensor products of 1D
   Lagrange shape functions on the W integer nodes.
+* The fractional index of a physical point in a donor grid is located here,
+  not taken from the problem description's inverse map: on a Cartesian grid
+  it is (x - origin) / spacing; on a curvilinear grid the nearest grid point
+  (a scan over all coordinates) starts a Newton iteration on the grid's
+  continuous mapping (whose integer samples are the grid's coordinates).
 """
 from __future__ import annotations
 
@@ -181,6 +186,62 @@ def lagrange_weights_1d(s: float, W: int) -> List[float]:
     return w
 
 
+def locate(grid, x: np.ndarray) -> np.ndarray:
+    """Fractional index (dim,) of the physical point x (dim,) in grid; NaN
+    components when it cannot be located (a curvilinear grid without a
+    mapping, or a Newton iteration that does not converge)."""
+    dim = grid.dim
+    x = np.asarray(x, dtype=np.float64).reshape(dim)
+    if grid.kind == 0:
+        return np.array([(x[d] - grid.origin[d]) / grid.spacing[d] for d in range(dim)])
+    if grid.mapping is None:
+        return np.full(dim, np.nan)
+    # start: the nearest grid point
+    d2 = np.zeros(grid.npts)
+    for d in range(dim):
+        d2 += (grid.coords[d] - x[d]) ** 2
+    p = int(np.argmin(d2))
+    xi = np.zeros(dim)
+    rest = p
+    for d in range(dim):
+        xi[d] = rest % grid.n[d]
+        rest //= grid.n[d]
+    # Newton on mapping(xi) = x with a central-difference Jacobian; the
+    # residual is exact, so the Jacobian's error only slows convergence
+    eps = 1e-6
+    polish = None
+    for _ in range(60):
+        res = grid.mapping(xi[:, None])[:, 0] - x
+        J = np.zeros((dim, dim))
+        for e in range(dim):
+            a = xi.copy()
+            b = xi.copy()
+            a[e] += eps
+            b[e] -= eps
+            J[:, e] = (grid.mapping(a[:, None])[:, 0] - grid.mapping(b[:, None])[:, 0]) / (2 * eps)
+        try:
+            step = np.linalg.solve(J, res)
+        except np.linalg.LinAlgError:
+            return np.full(dim, np.nan)
+        xi = xi - step
+        if not np.all(np.isfinite(xi)):
+            return np.full(dim, np.nan)
+        if polish is not None:
+            polish -= 1
+            if polish == 0:
+                break
+        elif np.max(np.abs(step)) < 1e-12:
+            polish = 2          # two more steps at the rounding floor
+    else:
+        return np.full(dim, np.nan)
+    if np.max(np.abs(grid.mapping(xi[:, None])[:, 0] - x)) > 1e-11 * (1.0 + np.max(np.abs(x))):
+        return np.full(dim, np.nan)
+    for d in range(dim):
+        if grid.periodic[d]:
+            xi[d] = xi[d] % grid.n[d]
+    return xi
+
+
 def donors(grids, iblanks, recv_lists, width: int):
     """For each receiving grid g: list of (donor grid id, point indices[W^dim],
     weights[W^dim]) in receiver order."""
@@ -197,7 +258,7 @@ def donors(grids, iblanks, recv_lists, width: int):
                 if dg == g:
                     continue
                 dgrid = grids[dg]
-                f = dgrid.frac_index(x)[:, 0]
+                f = locate(dgrid, x[:, 0])
                 if not np.all(np.isfinite(f)):
                     continue
                 idx1d, w1d, ok = [], [], True

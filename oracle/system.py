@@ -200,7 +200,41 @@ class OracleSystem:
             raise RuntimeError("orc_donor failed")
         return out
 
+    def _donor_arrays(self, g: int):
+        """Receivers of grid g grouped by donor grid: [(dg, receiver rows,
+        donor points (K, S), weights (K, S))], built once."""
+        if not hasattr(self, "_darr"):
+            self._darr = {}
+        if g not in self._darr:
+            groups: Dict[int, list] = {}
+            for r, (dg, pts, wts) in enumerate(self.donor_tables[g]):
+                groups.setdefault(dg, []).append((r, pts, wts))
+            out = []
+            for dg, items in sorted(groups.items()):
+                rows = np.array([it[0] for it in items], dtype=np.int64)
+                pts = np.array([it[1] for it in items], dtype=np.int64)
+                wts = np.array([it[2] for it in items], dtype=np.float64)
+                out.append((dg, rows, pts, wts))
+            self._darr[g] = out
+        return self._darr[g]
+
     def receiver_data(self, g: int, states: List[np.ndarray]) -> np.ndarray:
+        """q_hat and F_hat^V per receiver of grid g: each receiver's weighted
+        sum taken over its stencil entries in stencil order (acc = acc +
+        w_e * row_e), for all receivers of one donor grid at once."""
+        out = np.zeros((len(self.donor_tables[g]), self.RB))
+        for dg, rows, pts, wts in self._donor_arrays(g):
+            u = np.unique(pts)
+            v = self.donor_values(dg, states[dg], u)
+            vals = v[np.searchsorted(u, pts)]            # (K, S, RB)
+            acc = np.zeros((len(rows), self.RB))
+            for e in range(pts.shape[1]):
+                acc = acc + wts[:, e:e + 1] * vals[:, e, :]
+            out[rows] = acc
+        return out
+
+    def receiver_data_loop(self, g: int, states: List[np.ndarray]) -> np.ndarray:
+        """receiver_data written receiver by receiver (the plain loop)."""
         entries = self.donor_tables[g]
         out = np.zeros((len(entries), self.RB))
         if not entries:

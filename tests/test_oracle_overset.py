@@ -123,3 +123,129 @@ def test_short_runs_are_rejected():
     assert info[0][1].max() == 7
     with pytest.raises(overset.AssemblyError):
         overset.runs(g, ib, 42)
+
+
+# ---------------------------------------------------------------- curvilinear donors
+def test_omesh_mapping_samples_are_the_coordinates():
+    """The O-mesh coordinates are the continuous mapping at integer indices."""
+    g = workloads.cylinder(nbg=64, ntheta=96, nr=40, half=6.0).grids[1]
+    I, J = np.meshgrid(np.arange(g.n[0]), np.arange(g.n[1]), indexing="xy")
+    F = np.stack([I.ravel(), J.ravel()]).astype(float)
+    assert np.array_equal(g.mapping(F), g.coords)
+
+
+def test_omesh_inverse_returns_integer_indices_and_midpoints():
+    """The closed-form inverse the product locates donors with returns the
+    integer index at every O-mesh point and the fractional index at cell
+    midpoints (theta modulo the period)."""
+    g = workloads.cylinder().grids[1]
+    nth = g.n[0]
+    I, J = np.meshgrid(np.arange(g.n[0]), np.arange(g.n[1]), indexing="xy")
+    for off in (0.0, 0.5):
+        F = np.stack([I.ravel(), J.ravel()]).astype(float) + off
+        F = F[:, F[1] <= g.n[1] - 1]
+        got = g.inverse(g.mapping(F))
+        di = np.mod(got[0] - F[0] + nth / 2, nth) - nth / 2
+        assert np.max(np.abs(di)) < 1e-10
+        assert np.max(np.abs(got[1] - F[1])) < 1e-10
+
+
+def test_oracle_locate_inverts_the_mapping():
+    """The oracle's own search (nearest point, then Newton) recovers random
+    fractional indices, including next to the periodic seam."""
+    g = workloads.cylinder(nbg=64, ntheta=96, nr=40, half=6.0).grids[1]
+    rng = np.random.default_rng(5)
+    F = np.stack([rng.uniform(0, g.n[0], 200), rng.uniform(0, g.n[1] - 1, 200)])
+    F[0, :4] = [0.0, 1e-9, g.n[0] - 1e-9, 0.5]
+    X = g.mapping(F)
+    for k in range(F.shape[1]):
+        f = overset.locate(g, X[:, k])
+        di = (f[0] - F[0, k] + g.n[0] / 2) % g.n[0] - g.n[0] / 2
+        assert abs(di) < 1e-9 and abs(f[1] - F[1, k]) < 1e-9, (k, f, F[:, k])
+
+
+def _unwrapped_indices(grid, pts):
+    """Index coordinates (dim, S) of a donor stencil's points, periodic
+    directions unwrapped next to the first entry."""
+    out = []
+    rest = np.asarray(pts, dtype=np.int64)
+    for d in range(grid.dim):
+        i = (rest % grid.n[d]).astype(float)
+        rest = rest // grid.n[d]
+        if grid.periodic[d]:
+            i = i[0] + (np.mod(i - i[0] + grid.n[d] / 2, grid.n[d]) - grid.n[d] / 2)
+        out.append(i)
+    return np.stack(out)
+
+
+def test_curvilinear_donor_weights_reproduce_index_polynomials_and_location():
+    """Cylinder: every background receiver's O-mesh stencil reproduces the
+    index coordinates to degree 3 per direction (cubic Lagrange), and the
+    mapping at the interpolated index is the receiver's own position."""
+    wl = workloads.cylinder()
+    s = OracleSystem(wl)
+    om = wl.grids[1]
+    X = wl.grids[0].points()
+    n_checked = 0
+    for r, p in enumerate(s.grids[0].recv_pts):
+        dg, pts, wts = s.donor_tables[0][r]
+        assert dg == 1
+        F = _unwrapped_indices(om, pts)
+        wts = np.asarray(wts)
+        fhat = F @ wts
+        for d in range(2):
+            for k in range(4):
+                assert abs(np.dot(wts, F[d] ** k) - fhat[d] ** k) < 1e-9 * max(1.0, abs(fhat[d]) ** k)
+        xr = om.mapping(fhat[:, None])[:, 0]
+        assert np.max(np.abs(xr - X[:, p])) < 1e-12
+        n_checked += 1
+    assert n_checked > 100
+
+
+@pytest.mark.parametrize("size", ["small", "full"])
+def test_donor_tables_agree_with_product_assembly(size):
+    """The oracle's donor search (its own location, loops) and the product's
+    (closed-form inverse, whole-array numpy) give the same receivers, the
+    same donor grids and the same interpolation weights (as sparse vectors
+    over donor points, so that a stencil base shifted at a node would still
+    compare) on the cylinder."""
+    from paper_1805_06607_amd import assemble
+    wl = (workloads.cylinder(nbg=128, ntheta=96, nr=48) if size == "small"
+          else workloads.cylinder())
+    s = OracleSystem(wl)
+    ibs = [assemble.iblank(g) for g in wl.grids]
+    recs = [assemble.receivers(g, ib) for g, ib in zip(wl.grids, ibs)]
+    prod = assemble.donors(wl.grids, ibs, recs, wl.params["interp_width"])
+    for g in range(len(wl.grids)):
+        assert np.array_equal(s.grids[g].iblank, ibs[g])
+        assert np.array_equal(s.grids[g].recv_pts, recs[g])
+        pmap = {}
+        for dg, (rr, pp, ww) in prod[g].items():
+            for k in range(len(rr)):
+                pmap[int(rr[k])] = (dg, pp[k], ww[k])
+        for r, p in enumerate(s.grids[g].recv_pts):
+            dg, pts, wts = s.donor_tables[g][r]
+            pdg, ppts, pw = pmap[int(p)]
+            assert dg == pdg
+            a, b = {}, {}
+            for q, w in zip(pts, wts):
+                a[int(q)] = a.get(int(q), 0.0) + w
+            for q, w in zip(ppts, pw):
+                b[int(q)] = b.get(int(q), 0.0) + w
+            for k in set(a) | set(b):
+                assert abs(a.get(k, 0.0) - b.get(k, 0.0)) < 1e-12, (g, p, k)
+
+
+@pytest.mark.parametrize("case", ["vortex_box", "cylinder_small", "tgv3d_small"])
+def test_receiver_data_vectorised_equals_loop_bitwise(case):
+    """The oracle's receiver data over all receivers at once takes each
+    receiver's stencil sum in the same order as the receiver-by-receiver loop."""
+    wl = {"vortex_box": lambda: workloads.vortex_box(),
+          "cylinder_small": lambda: workloads.cylinder(nbg=96, ntheta=64, nr=32, half=6.0),
+          "tgv3d_small": lambda: workloads.tgv3d(nbg=48, npatch=24, ninner=16)}[case]()
+    s = OracleSystem(wl)
+    states = workloads.random_state_like(wl, seed=9, amp=0.02)
+    for g in range(len(wl.grids)):
+        a = s.receiver_data(g, states)
+        b = s.receiver_data_loop(g, states)
+        assert np.array_equal(a, b)

@@ -12,9 +12,11 @@ Geometry conventions
 * Points are numbered x fastest: flat index ``p = i + nx*(j + ny*k)``.
 * A Cartesian grid has ``x_d(i_d) = origin[d] + i_d*spacing[d]``.
 * A curvilinear grid carries explicit coordinates ``coords`` of shape
-  ``(dim, N)`` and an analytic inverse map used to locate donor cells.
-* ``inverse(X)`` maps physical points ``X`` (shape ``(dim, K)``) to fractional
-  grid indices (shape ``(dim, K)``); it is a property of the grid mapping.
+  ``(dim, N)``, sampled at the integer indices of its continuous mapping
+  ``mapping(F)`` (fractional indices ``F`` of shape ``(dim, K)`` to physical
+  points), and the closed-form inverse of that mapping, ``inverse(X)``
+  (physical points to fractional indices).  Both describe the grid's geometry;
+  which of them a consumer uses to locate donor cells is its own choice.
 * Holes are shapes; a point strictly inside any of its grid's shapes is blanked.
 
 The problems follow the paper's workloads: the convecting isentropic vortex
@@ -54,6 +56,7 @@ class Grid:
     spacing: tuple = (1.0, 1.0, 1.0)
     coords: Optional[np.ndarray] = None     # (dim, N) for curvilinear grids
     inverse: Optional[Callable] = None      # X (dim,K) -> fractional index (dim,K)
+    mapping: Optional[Callable] = None      # fractional index (dim,K) -> X (dim,K)
     holes: list = field(default_factory=list)   # ('box', lo, hi) | ('disk', c, r)
     # coordinate jump across the seam of each periodic direction (curvilinear
     # grids on a translation-periodic domain): x(i_d + n_d) = x(i_d) + coord_period[d]
@@ -215,6 +218,13 @@ def omesh_grid(ntheta: int, nr: int, rate: int, priority: int, wall: bool = True
     coords = np.stack([(R * np.cos(TH)).ravel(), (R * np.sin(TH)).ravel()])
     dr0 = (r1 - r0) * (stretch - 1.0) / (stretch ** (nr - 1) - 1.0)
 
+    def mapping(F, ntheta=ntheta, dr0=dr0):
+        # theta = 2 pi i / ntheta, r = r0 + dr0 (stretch^j - 1) / (stretch - 1)
+        F = np.asarray(F, dtype=np.float64)
+        tt = 2.0 * math.pi * F[0] / ntheta
+        rr = r0 + dr0 * (stretch ** F[1] - 1.0) / (stretch - 1.0)
+        return np.stack([rr * np.cos(tt), rr * np.sin(tt)])
+
     def inverse(X, ntheta=ntheta, dr0=dr0):
         rr = np.hypot(X[0], X[1])
         tt = np.mod(np.arctan2(X[1], X[0]), 2.0 * math.pi)
@@ -226,7 +236,7 @@ def omesh_grid(ntheta: int, nr: int, rate: int, priority: int, wall: bool = True
     bc_lo = BC_WALL if wall else BC_FARFIELD
     return Grid("omesh", (ntheta, nr), (True, False), CURVILINEAR,
                 [BC_PERIODIC, BC_PERIODIC, bc_lo, outer_bc], rate, priority,
-                coords=coords, inverse=inverse)
+                coords=coords, inverse=inverse, mapping=mapping)
 
 
 def cylinder(nbg: int = 512, ntheta: int = 256, nr: int = 128, half: float = 20.0,
