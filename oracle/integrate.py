@@ -137,3 +137,19 @@ def srab_steps(rhs: Callable, y: List[np.ndarray], hist: List[List[np.ndarray]],
         for g in range(G):
             hist[g] = hist[g][1:] + [F[g]]
     return y, hist
+
+
+def rk4_steps(rhs: Callable, y: List[np.ndarray], h: float, nsteps: int) -> List[np.ndarray]:
+    """Classic fourth-order Runge-Kutta, every level at step h (the reference
+    integrator of section "Multi-Rate Adams-Bashforth Accuracy and
+    Convergence")."""
+    G = len(y)
+    allg = list(range(G))
+    y = [a.copy() for a in y]
+    for _ in range(nsteps):
+        k1 = rhs(y, allg)
+        k2 = rhs([y[g] + (h / 2.0) * k1[g] for g in allg], allg)
+        k3 = rhs([y[g] + (h / 2.0) * k2[g] for g in allg], allg)
+        k4 = rhs([y[g] + h * k3[g] for g in allg], allg)
+        y = [y[g] + (h / 6.0) * (k1[g] + 2.0 * k2[g] + 2.0 * k3[g] + k4[g]) for g in allg]
+    return y

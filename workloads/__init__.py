@@ -424,6 +424,25 @@ def omesh_freestream(ntheta: int = 64, nr: int = 24, sbp: int = 42) -> Workload:
     return Workload("omesh_freestream", 2, params, [g], q0)
 
 
+def wall_channel(ny: int, nx: int = 8, Re: float = 100.0, mach: float = 0.2, wall_temp_ratio: float = 1.05,
+                 sbp: int = 42) -> Workload:
+    """Channel periodic in x with isothermal no-slip walls at y = 0 and y = 1,
+    started impulsively: uniform u = 1, v = 0, rho = 1, p = 1/(gamma M^2),
+    walls at wall_temp_ratio times the initial temperature."""
+    gamma = 1.4
+    h = 1.0 / (ny - 1)
+    g = Grid("channel", (nx, ny), (True, False), CARTESIAN, [BC_PERIODIC, BC_PERIODIC, BC_WALL, BC_WALL],
+             1, 0, origin=(0.0, 0.0, 0.0), spacing=(h, h, h))
+    p = 1.0 / (gamma * mach * mach)
+    params = default_params(gamma=gamma, Re=Re, sbp=sbp, order=4, hist_len=4,
+                            interp_width=4 if sbp == 42 else 2)
+    params["T_wall"] = wall_temp_ratio * p
+    params["q_inf"] = [1.0, 1.0, 0.0, p / (gamma - 1.0) + 0.5, 0.0]
+    one = np.ones(g.npts)
+    q0 = [conserved_from_primitive(one, [one, 0.0 * one], p * one, gamma)]
+    return Workload("wall_channel", 2, params, [g], q0)
+
+
 def random_state_like(wl: Workload, seed: int, amp: float = 0.05) -> List[np.ndarray]:
     """Seeded smooth-free perturbation of a workload's initial state (for
     element-wise parity of one right-hand side on non-trivial data)."""
