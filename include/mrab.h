@@ -19,7 +19,9 @@
  *  - All device work is enqueued on the HIP stream given to mr_create; calls
  *    marked "async" do not synchronise the host.  Setup calls may synchronise.
  *  - The library never allocates device memory: mr_finalize reports the
- *    workspace size and the caller binds one buffer with mr_bind_workspace.
+ *    workspace size and the caller binds one buffer with mr_bind_workspace
+ *    (or, for small systems, the library's static per-device array with
+ *    mr_bind_static_workspace).
  *  - A context is not thread-safe; distinct contexts are independent.
  */
 #ifndef MRAB_H
@@ -127,6 +129,26 @@ int mr_finalize(mr_ctx *ctx, size_t *workspace_bytes);
 /* Bind caller-owned device memory (>= the reported size, 256-byte aligned),
  * upload the tables, compute metric terms on the device. */
 int mr_bind_workspace(mr_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Size of the library's static workspace: one array of this many bytes per
+ * device, held from the load of the library's code object until the process
+ * ends. */
+#define MR_STATIC_WORKSPACE_BYTES ((size_t)16 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, allocation-free serving loops, harnesses that forbid hipMalloc):
+ * mr_bind_workspace with the library's own static array on the device of the
+ * context's stream (the current device for the default stream) in place of
+ * caller memory.  Calls no hipMalloc, hipFree or other allocating routine; the
+ * array is cleared and the tables uploaded exactly as mr_bind_workspace does.
+ * The array is shared: binding it to a context takes it from the context that
+ * held it on that device, whose later calls fail with MR_ERR_STATE; calls of
+ * two contexts that overlap on one device race.  Released by mr_destroy of
+ * its holder.
+ * Errors: MR_ERR_ARG (the reported workspace exceeds
+ * MR_STATIC_WORKSPACE_BYTES: bind caller memory instead), MR_ERR_STATE (before
+ * mr_finalize or already bound), MR_ERR_HIP. */
+int mr_bind_static_workspace(mr_ctx *ctx);
 
 /* Copy a grid state (device, nv x npts) into / out of the context (async).
  * After mr_set_state (or mr_set_history) macrosteps need mr_mrab_start or

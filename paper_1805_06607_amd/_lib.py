@@ -46,6 +46,7 @@ SIGNATURES = {
                        POINTER(c_double)],
     "mr_finalize": [c_void_p, POINTER(c_size_t)],
     "mr_bind_workspace": [c_void_p, c_void_p, c_size_t],
+    "mr_bind_static_workspace": [c_void_p],
     "mr_set_state": [c_void_p, c_int, c_void_p],
     "mr_get_state": [c_void_p, c_int, c_void_p],
     "mr_rhs": [c_void_p, c_double, POINTER(c_void_p), POINTER(c_void_p)],

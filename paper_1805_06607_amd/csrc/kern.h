@@ -185,4 +185,8 @@ hipError_t launch_wait_us(double us, hipStream_t st);
 // block-partial reductions: mode 0 = min, 1 = max |x| (NaN/Inf -> +inf)
 hipError_t launch_reduce(int64_t n, const double *x, int mode, double *partial, int nblocks, hipStream_t st);
 
+// device address of the library's static workspace on `device`
+// (MR_STATIC_WORKSPACE_BYTES bytes, 256-byte aligned), looked up once per device
+hipError_t static_workspace(int device, void **ptr);
+
 }  // namespace mrk

@@ -7,10 +7,13 @@
 // Accuracy of Right-Hand Sides"), second derivatives as two applications of
 // the first-derivative SBP operator (same Appendix), SAT interface penalty
 // eq. (int), AB combination eq. (ab_general), timestep eq. (ts_inv)-(ts_overall).
+#include "mrab.h"
 #include "kern.h"
 #include "sbp_dev.h"
 
 #include <math.h>
+#include <map>
+#include <mutex>
 
 namespace mrk {
 
@@ -1788,6 +1791,44 @@ hipError_t launch_reduce(int64_t n, const double *x, int mode, double *partial, 
 {
     hipLaunchKernelGGL(k_reduce, dim3(nblocks), dim3(256), 0, st, n, x, mode, partial);
     return hipGetLastError();
+}
+
+}  // namespace mrk
+
+// Library-owned workspace for callers that cannot allocate device memory
+// (mr_bind_static_workspace).  Every device the library runs on holds its own
+// copy from the load of the code object until the process ends.  Host code
+// never uses this name as an address: the device address comes from
+// hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[MR_STATIC_WORKSPACE_BYTES];
+
+namespace mrk {
+
+hipError_t static_workspace(int device, void **ptr)
+{
+    static std::mutex mu;
+    static std::map<int, void *> addr;   // device -> address of its copy of the array
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it != addr.end()) {
+        *ptr = it->second;
+        return hipSuccess;
+    }
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) {
+        hipError_t e2 = hipSetDevice(cur);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    if (!p || (uintptr_t)p % 256) return hipErrorInvalidValue;
+    addr[device] = p;
+    *ptr = p;
+    return hipSuccess;
 }
 
 }  // namespace mrk

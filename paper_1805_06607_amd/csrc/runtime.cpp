@@ -12,6 +12,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -157,6 +159,7 @@ struct mr_ctx {
     EvSet eager;
     std::vector<hipEvent_t> ev;
     AdjCtx *adj = nullptr;                     // discrete adjoint (mr_adj_*)
+    int static_dev = -1;                       // device whose static workspace is bound, -1: caller memory
 };
 
 // Many independent systems advanced together: per micro-time of the batch,
@@ -194,6 +197,28 @@ int fail(mr_ctx *c, int code, const char *fmt, ...)
     va_end(ap);
     if (c) c->err = buf;
     return code;
+}
+
+// holder of each device's static workspace (mr_bind_static_workspace)
+std::mutex g_static_mu;
+std::map<int, const mr_ctx *> g_static_holder;
+
+bool static_lost(const mr_ctx *c)
+{
+    if (c->static_dev < 0) return false;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    auto it = g_static_holder.find(c->static_dev);
+    return it == g_static_holder.end() || it->second != c;
+}
+
+// MR_OK when the context's workspace is bound and still its own
+int need_bound(mr_ctx *c, const char *what)
+{
+    if (!c->bound) return fail(c, MR_ERR_STATE, "%s before mr_bind_workspace", what);
+    if (static_lost(c))
+        return fail(c, MR_ERR_STATE, "%s: the static workspace of device %d is bound to another context", what,
+                    c->static_dev);
+    return MR_OK;
 }
 
 #define HIPCHK(c, expr)                                                                     \
@@ -2063,6 +2088,7 @@ int adj_reverse(mr_ctx *c, const Sched &S, int a, int b, int sa, int s, int nmac
 int adj_check(mr_ctx *c, int nmacro)
 {
     if (!c->adj || !c->adj->bound) return fail(c, MR_ERR_STATE, "adjoint workspace not bound");
+    if (int rc_ = need_bound(c, "the adjoint")) return rc_;
     if (!c->have_dt) return fail(c, MR_ERR_STATE, "no macrostep set (mr_timestep or mr_set_macrostep)");
     if (nmacro < 0) return fail(c, MR_ERR_ARG, "negative macrostep count");
     return MR_OK;
@@ -2260,13 +2286,13 @@ int mr_finalize(mr_ctx *c, size_t *bytes)
     return MR_OK;
 }
 
-int mr_bind_workspace(mr_ctx *c, void *dev, size_t bytes)
+}  // extern "C"
+
+namespace {
+
+// clear the workspace, upload the tables, compute the metric terms
+int bind_at(mr_ctx *c, void *dev)
 {
-    if (!c || !dev) return MR_ERR_ARG;
-    if (!c->finalized) return fail(c, MR_ERR_STATE, "mr_bind_workspace before mr_finalize");
-    if (c->bound) return fail(c, MR_ERR_STATE, "workspace already bound");
-    if (bytes < c->ws_bytes) return fail(c, MR_ERR_ARG, "workspace too small (%zu < %zu)", bytes, c->ws_bytes);
-    if ((uintptr_t)dev % ALIGN) return fail(c, MR_ERR_ARG, "workspace not 256-byte aligned");
     c->ws = (char *)dev;
     layout(c, c->ws);
     HIPCHK(c, hipMemsetAsync(c->ws, 0, c->ws_bytes, c->st));
@@ -2326,10 +2352,51 @@ int mr_bind_workspace(mr_ctx *c, void *dev, size_t bytes)
     return MR_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int mr_bind_workspace(mr_ctx *c, void *dev, size_t bytes)
+{
+    if (!c || !dev) return MR_ERR_ARG;
+    if (!c->finalized) return fail(c, MR_ERR_STATE, "mr_bind_workspace before mr_finalize");
+    if (c->bound) return fail(c, MR_ERR_STATE, "workspace already bound");
+    if (bytes < c->ws_bytes) return fail(c, MR_ERR_ARG, "workspace too small (%zu < %zu)", bytes, c->ws_bytes);
+    if ((uintptr_t)dev % ALIGN) return fail(c, MR_ERR_ARG, "workspace not 256-byte aligned");
+    return bind_at(c, dev);
+}
+
+int mr_bind_static_workspace(mr_ctx *c)
+{
+    if (!c) return MR_ERR_ARG;
+    if (!c->finalized) return fail(c, MR_ERR_STATE, "mr_bind_static_workspace before mr_finalize");
+    if (c->bound) return fail(c, MR_ERR_STATE, "workspace already bound");
+    if (c->ws_bytes > MR_STATIC_WORKSPACE_BYTES)
+        return fail(c, MR_ERR_ARG,
+                    "workspace of %zu bytes exceeds the static workspace (%zu bytes): bind caller memory "
+                    "with mr_bind_workspace",
+                    c->ws_bytes, (size_t)MR_STATIC_WORKSPACE_BYTES);
+    int dev = 0;
+    if (c->st) {
+        HIPCHK(c, hipStreamGetDevice(c->st, &dev));
+    } else {
+        HIPCHK(c, hipGetDevice(&dev));
+    }
+    void *p = nullptr;
+    HIPCHK(c, mrk::static_workspace(dev, &p));
+    {
+        // the previous holder's later calls fail; it must not be running now
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        g_static_holder[dev] = c;
+    }
+    c->static_dev = dev;
+    return bind_at(c, p);
+}
+
 int mr_set_state(mr_ctx *c, int g, const double *q)
 {
     if (!c || !q || g < 0 || g >= (int)c->G.size()) return MR_ERR_ARG;
-    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_set_state before mr_bind_workspace");
+    if (int rc_ = need_bound(c, "mr_set_state")) return rc_;
     GridHost &G = c->G[g];
     HIPCHK(c, hipMemcpyAsync(G.y[G.cur], q, nelem(G) * 8, hipMemcpyDeviceToDevice, c->st));
     c->stale = true;
@@ -2339,7 +2406,7 @@ int mr_set_state(mr_ctx *c, int g, const double *q)
 int mr_get_state(mr_ctx *c, int g, double *q)
 {
     if (!c || !q || g < 0 || g >= (int)c->G.size()) return MR_ERR_ARG;
-    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_get_state before mr_bind_workspace");
+    if (int rc_ = need_bound(c, "mr_get_state")) return rc_;
     GridHost &G = c->G[g];
     HIPCHK(c, hipMemcpyAsync(q, G.y[G.cur], nelem(G) * 8, hipMemcpyDeviceToDevice, c->st));
     return MR_OK;
@@ -2348,7 +2415,7 @@ int mr_get_state(mr_ctx *c, int g, double *q)
 int mr_rhs(mr_ctx *c, double, const double *const *q, double *const *F)
 {
     if (!c || !q || !F) return MR_ERR_ARG;
-    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_rhs before mr_bind_workspace");
+    if (int rc_ = need_bound(c, "mr_rhs")) return rc_;
     for (size_t g = 0; g < c->G.size(); ++g)
         if (!q[g] || !F[g]) return fail(c, MR_ERR_ARG, "null state or output pointer");
     return rhs_all(c, q, F);
@@ -2364,7 +2431,7 @@ int mr_num_receivers(const mr_ctx *c, int g, int64_t *n)
 int mr_receiver_data(mr_ctx *c, int g, const double *const *q, double *out)
 {
     if (!c || !q || !out || g < 0 || g >= (int)c->G.size()) return MR_ERR_ARG;
-    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_receiver_data before mr_bind_workspace");
+    if (int rc_ = need_bound(c, "mr_receiver_data")) return rc_;
     for (const Link &L : c->links) {
         if (L.rg != g) continue;
         if (!q[L.dg]) return fail(c, MR_ERR_ARG, "null donor state");
@@ -2378,7 +2445,7 @@ int mr_timestep(mr_ctx *c, double *h, double *H)
 {
     if (c) c->version++;
     if (!c) return MR_ERR_ARG;
-    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_timestep before mr_bind_workspace");
+    if (int rc_ = need_bound(c, "mr_timestep")) return rc_;
     double Hm;
     if (c->P.dt_fixed > 0) {
         Hm = c->P.dt_fixed;
@@ -2407,7 +2474,7 @@ int mr_mrab_start(mr_ctx *c, double t0)
 {
     if (c) c->version++;
     if (!c) return MR_ERR_ARG;
-    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_mrab_start before mr_bind_workspace");
+    if (int rc_ = need_bound(c, "mr_mrab_start")) return rc_;
     if (!c->have_dt) {
         int rc = mr_timestep(c, nullptr, nullptr);
         if (rc) return rc;
@@ -2472,6 +2539,7 @@ int mr_mrab_macrostep(mr_ctx *c, int nsteps)
 {
     if (!c || nsteps < 0) return MR_ERR_ARG;
     if (!c->started) return fail(c, MR_ERR_STATE, "mr_mrab_macrostep before mr_mrab_start");
+    if (int rc_ = need_bound(c, "mr_mrab_macrostep")) return rc_;
     if (c->stale) return fail(c, MR_ERR_STATE, "state or history set: call mr_mrab_resume or mr_mrab_start first");
     if (nsteps == 0) return MR_OK;
     int64_t npts = 0;
@@ -2499,6 +2567,7 @@ int mr_set_history(mr_ctx *c, int g, int j, const double *in)
 {
     if (!c || !in || g < 0 || g >= (int)c->G.size() || j < 0 || j >= c->P.hist_len) return MR_ERR_ARG;
     if (!c->started) return fail(c, MR_ERR_STATE, "mr_set_history before mr_mrab_start");
+    if (int rc_ = need_bound(c, "mr_set_history")) return rc_;
     GridHost &G = c->G[g];
     HIPCHK(c, hipMemcpyAsync(slot(c, G, j), in, nelem(G) * 8, hipMemcpyDeviceToDevice, c->st));
     c->stale = true;
@@ -2510,6 +2579,7 @@ int mr_mrab_resume(mr_ctx *c, double t)
     if (c) c->version++;
     if (!c) return MR_ERR_ARG;
     if (!c->started) return fail(c, MR_ERR_STATE, "mr_mrab_resume before mr_mrab_start");
+    if (int rc_ = need_bound(c, "mr_mrab_resume")) return rc_;
     int rc = restage(c);
     if (rc) return rc;
     c->t = t;
@@ -2522,6 +2592,7 @@ int mr_get_history(mr_ctx *c, int g, int j, double *out)
 {
     if (!c || !out || g < 0 || g >= (int)c->G.size() || j < 0 || j >= c->P.hist_len) return MR_ERR_ARG;
     if (!c->started) return fail(c, MR_ERR_STATE, "mr_get_history before mr_mrab_start");
+    if (int rc_ = need_bound(c, "mr_get_history")) return rc_;
     GridHost &G = c->G[g];
     HIPCHK(c, hipMemcpyAsync(out, slot(c, G, j), nelem(G) * 8, hipMemcpyDeviceToDevice, c->st));
     return MR_OK;
@@ -2627,6 +2698,7 @@ int mr_save(mr_ctx *c, void *dev, size_t bytes)
 {
     if (!c || !dev) return MR_ERR_ARG;
     if (!c->started) return fail(c, MR_ERR_STATE, "mr_save before mr_mrab_start");
+    if (int rc_ = need_bound(c, "mr_save")) return rc_;
     if (c->stale) return fail(c, MR_ERR_STATE, "state or history set since the last start/resume");
     const size_t need = save_bytes(c);
     if (bytes < need) return fail(c, MR_ERR_ARG, "checkpoint buffer too small (%zu < %zu)", bytes, need);
@@ -2662,7 +2734,7 @@ int mr_load(mr_ctx *c, const void *dev, size_t bytes)
 {
     if (c) c->version++;
     if (!c || !dev) return MR_ERR_ARG;
-    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_load before mr_bind_workspace");
+    if (int rc_ = need_bound(c, "mr_load")) return rc_;
     if (bytes < sizeof(SaveHeader)) return fail(c, MR_ERR_ARG, "checkpoint buffer too small");
     if ((uintptr_t)dev % 8) return fail(c, MR_ERR_ARG, "checkpoint buffer not 8-byte aligned");
     SaveHeader h{};
@@ -2753,7 +2825,7 @@ int mr_autotune(mr_ctx *c, int reps)
 {
     if (c) c->version++;
     if (!c || reps < 1 || reps > 1000) return MR_ERR_ARG;
-    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_autotune before mr_bind_workspace");
+    if (int rc_ = need_bound(c, "mr_autotune")) return rc_;
     if (c->two_pass) return MR_OK;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
@@ -2798,7 +2870,7 @@ int mr_autotune(mr_ctx *c, int reps)
 int mr_guard(mr_ctx *c, double *maxabs)
 {
     if (!c) return MR_ERR_ARG;
-    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_guard before mr_bind_workspace");
+    if (int rc_ = need_bound(c, "mr_guard")) return rc_;
     double mx = 0;
     for (auto &g : c->G) {
         HIPCHK(c, mrk::launch_reduce(nelem(g), g.y[g.cur], 1, c->partial, 256, c->st));
@@ -2880,6 +2952,7 @@ int mr_batch_macrostep(mr_batch *b, int nsteps)
     for (int s = 0; s < n; ++s) {
         const mr_ctx *c = b->ctx[s];
         if (!c->started || c->stale) return bfail(b, MR_ERR_STATE, "a system is not started (or needs mr_mrab_resume)");
+        if (static_lost(c)) return bfail(b, MR_ERR_STATE, "a system's static workspace is bound to another context");
         if (b->built && (c->version != b->version[s] || c->nmacro != b->base[s] + b->steps)) rebuild = true;
     }
     if (rebuild) {
@@ -2966,7 +3039,7 @@ int mr_adj_workspace_size(mr_ctx *c, int nsnap, size_t *bytes)
 int mr_adj_bind_workspace(mr_ctx *c, void *dev, size_t bytes)
 {
     if (!c || !dev) return MR_ERR_ARG;
-    if (!c->bound) return fail(c, MR_ERR_STATE, "mr_adj_bind_workspace before mr_bind_workspace");
+    if (int rc_ = need_bound(c, "mr_adj_bind_workspace")) return rc_;
     if (!c->adj || !c->adj->bytes) return fail(c, MR_ERR_STATE, "mr_adj_bind_workspace before mr_adj_workspace_size");
     AdjCtx &A = *c->adj;
     if (A.bound) return fail(c, MR_ERR_STATE, "adjoint workspace already bound");
@@ -3004,6 +3077,7 @@ int mr_adj_rhs(mr_ctx *c, const double *const *q, const double *const *lamF, dou
 {
     if (!c || !q || !lamF || !lam_q) return MR_ERR_ARG;
     if (!c->adj || !c->adj->bound) return fail(c, MR_ERR_STATE, "adjoint workspace not bound");
+    if (int rc_ = need_bound(c, "the adjoint")) return rc_;
     const int G = (int)c->G.size();
     std::vector<double *> Y(G), K(G), LF(G), LQ(G);
     for (int g = 0; g < G; ++g) {
@@ -3125,6 +3199,11 @@ void mr_destroy(mr_ctx *c)
     for (auto s : c->gs)
         if (s) (void)hipStreamDestroy(s);
     delete c->adj;
+    if (c->static_dev >= 0) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        auto it = g_static_holder.find(c->static_dev);
+        if (it != g_static_holder.end() && it->second == c) g_static_holder.erase(it);
+    }
     delete c;
 }
 

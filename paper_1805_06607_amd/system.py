@@ -45,7 +45,8 @@ class System:
     boundary flags, hole shapes, rates, parameters and initial states.
     """
 
-    def __init__(self, wl, device: str = "cuda:0", stream: Optional[torch.cuda.Stream] = None):
+    def __init__(self, wl, device: str = "cuda:0", stream: Optional[torch.cuda.Stream] = None,
+                 static_workspace: bool = False):
         self.lib = _lib.load()
         self.wl = wl
         self.device = torch.device(device)
@@ -105,11 +106,18 @@ class System:
             self.recv_order.append(np.array(order, dtype=np.int64))
         nbytes = c_size_t()
         self._check(self.lib.mr_finalize(self.ctx, byref(nbytes)), "mr_finalize")
-        self.ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
-        base = self.ws.data_ptr()
-        off = (-base) % 256
-        self._check(self.lib.mr_bind_workspace(self.ctx, c_void_p(base + off), c_size_t(nbytes.value)),
-                    "mr_bind_workspace")
+        self.workspace_bytes = int(nbytes.value)
+        if static_workspace:
+            # the library's own per-device array: no device allocation here
+            self.ws = None
+            with torch.cuda.device(self.device):
+                self._check(self.lib.mr_bind_static_workspace(self.ctx), "mr_bind_static_workspace")
+        else:
+            self.ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+            base = self.ws.data_ptr()
+            off = (-base) % 256
+            self._check(self.lib.mr_bind_workspace(self.ctx, c_void_p(base + off), c_size_t(nbytes.value)),
+                        "mr_bind_workspace")
         self.set_states([torch.as_tensor(q, dtype=torch.float64) for q in wl.q0])
 
     # ------------------------------------------------------------ helpers

@@ -64,6 +64,8 @@ def test_argument_validation_without_device():
     # call-order violations
     out = ctypes.c_size_t()
     assert lib.mr_finalize(ctx, ctypes.byref(out)) == -2
+    assert lib.mr_bind_static_workspace(ctx) == -2                     # before mr_finalize
+    assert lib.mr_bind_static_workspace(None) == -1
     assert lib.mr_save(ctx, ctypes.c_void_p(256), 1 << 20) == -2       # before mr_mrab_start
     assert lib.mr_load(ctx, ctypes.c_void_p(256), 1 << 20) == -2       # before mr_bind_workspace
     assert lib.mr_save(ctx, None, 0) == -1
@@ -72,3 +74,20 @@ def test_argument_validation_without_device():
     assert lib.mr_adj_bind_workspace(ctx, ctypes.c_void_p(256), 1 << 20) == -2
     assert lib.mr_adj_gradient(ctx, 1, None, None, 1.0, None, None, None) == -1
     lib.mr_destroy(ctx)
+
+
+def test_library_defines_no_unprefixed_c_functions():
+    """Every function the library defines with C linkage is an mr_ entry
+    point: an internal helper with C linkage could bind, at load time, to a
+    same-named routine of another library (or shadow one)."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    from paper_1805_06607_amd import _lib
+    out = subprocess.run([nm, "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    funcs = [ln.split()[-1] for ln in out.splitlines() if len(ln.split()) == 3 and ln.split()[1] in ("T", "W")]
+    bad = [f for f in funcs if not (f.startswith("mr_") or f.startswith("_Z") or f in ("_init", "_fini"))]
+    assert not bad, bad
