@@ -8,6 +8,10 @@ namespace mrk {
 
 constexpr int MAXG = 8;     // grids per context
 constexpr int MAXH = 8;     // history length
+// 3D grids store, per point, the viscous quantities a flux needs in place of
+// the 12 gradients: the stress tau_ij (symmetric: 6 values) and the heat
+// terms h_j = kc dT/dx_j (3)
+constexpr int NVISC3 = 9;
 
 // Class byte of a point along one direction:
 //   bits 0-3  row: 0 interior, 1..4 left closure row 0..3, 5..8 right closure row 0..3, 15 hole
@@ -119,7 +123,7 @@ struct Extrap {
 };
 
 // ---------------------------------------------------------------- launches
-hipError_t launch_grad(const GridDev &g, int sbp, double gm1, const double *q, double *grad, hipStream_t st);
+hipError_t launch_grad(const GridDev &g, int sbp, const Phys &ph, const double *q, double *grad, hipStream_t st);
 hipError_t launch_rhs(const GridDev &g, const GridDev *g_dev, int sbp, const Phys &ph, const double *q,
                       const double *grad, double *F, const Combine &cb, hipStream_t st);
 hipError_t launch_donor(const DonorLink &a, hipStream_t st);
@@ -169,6 +173,14 @@ extern const TileShape3 kTile3dShapes[NUM_TILE3D_SHAPES];
 // within a slab (<= 0 or >= the tile rows: the plain x, y, z order)
 hipError_t launch_rhs_tile3d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *grad,
                              double *F, const Combine &cb, int shape, int slab, hipStream_t st);
+// the same right-hand side with the flux pass marching along z (k_rhs_zm3d):
+// gradient pass on tiles of grad_shape (kTile3dShapes), flux pass on columns of
+// shape 1: 16 x 16, 2: 32 x 8, 3: 16 x 8, zc planes per chunk (0: chosen
+// from the grid size), then the SAT penalties of the nsat points satpts
+// (every active point that ends a run in some direction)
+hipError_t launch_rhs_zm3d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *vis, double *F,
+                           const Combine &cb, int grad_shape, int slab, int shape, int zc, const int32_t *satpts,
+                           int nsat, hipStream_t st);
 hipError_t launch_combine(int64_t n, const double *y, const Combine &cb, hipStream_t st);
 hipError_t launch_axpy(int64_t n, const double *y, double a, const double *x, double *out, hipStream_t st);
 hipError_t launch_rk3_final(int64_t n, const double *y, double a, const double *k1, const double *k3,

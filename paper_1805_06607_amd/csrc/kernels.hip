@@ -19,25 +19,34 @@ namespace mrk {
 
 // ------------------------------------------------------------ gradient pass
 template <int DIM, int SBP, int CART>
-__global__ void __launch_bounds__(256) k_grad(GridDev g, double gm1, const double *__restrict__ q,
+__global__ void __launch_bounds__(256) k_grad(GridDev g, Phys ph, const double *__restrict__ q,
                                               double *__restrict__ grad)
 {
+    const double gm1 = ph.gamma - 1.0;
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= g.npts) return;
     const int64_t N = g.npts;
+    constexpr int NG = DIM == 3 ? NVISC3 : DIM * (DIM + 1);
     if ((g.cls[p] & 15) == CLS_HOLE) {
 #pragma unroll
-        for (int k = 0; k < DIM * (DIM + 1); ++k) grad[k * N + p] = 0.0;
+        for (int k = 0; k < NG; ++k) grad[k * N + p] = 0.0;
         return;
     }
     int ic[3];
     coords(g, p, ic);
     double gr[DIM + 1][DIM];
     gradient<DIM, SBP, CART>(g, p, ic, gm1, [&](int64_t idx, double *o) { load_q<DIM>(q, N, idx, o); }, gr);
+    if constexpr (DIM == 3) {
+        double V[NVISC3];
+        visc3_from_grad(ph, gr, V);
 #pragma unroll
-    for (int a = 0; a <= DIM; ++a)
+        for (int k = 0; k < NVISC3; ++k) grad[(int64_t)k * N + p] = V[k];
+    } else {
 #pragma unroll
-        for (int j = 0; j < DIM; ++j) grad[(int64_t)(a * DIM + j) * N + p] = gr[a][j];
+        for (int a = 0; a <= DIM; ++a)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) grad[(int64_t)(a * DIM + j) * N + p] = gr[a][j];
+    }
 }
 
 // --------------------------------------------- fused flux divergence + SAT + AB
@@ -57,13 +66,20 @@ __device__ __forceinline__ Vec<DIM + 2> fhat_at(const GridDev &g, const Phys &ph
 #pragma unroll
     for (int i = 0; i < DIM; ++i) { u[i] = qq[1 + i] * ri; ke += u[i] * qq[1 + i]; }
     double pr = gm1 * (qq[DIM + 1] - 0.5 * ke);
-    double gr[DIM + 1][DIM];
-#pragma unroll
-    for (int a = 0; a <= DIM; ++a)
-#pragma unroll
-        for (int j = 0; j < DIM; ++j) gr[a][j] = grad[(int64_t)(a * DIM + j) * N + idx];
     double Fv[DIM][DIM + 1];
-    viscous_flux<DIM>(ph, u, gr, Fv);
+    if constexpr (DIM == 3) {
+        double V[NVISC3];
+#pragma unroll
+        for (int k = 0; k < NVISC3; ++k) V[k] = grad[(int64_t)k * N + idx];
+        viscous_flux3(u, V, Fv);
+    } else {
+        double gr[DIM + 1][DIM];
+#pragma unroll
+        for (int a = 0; a <= DIM; ++a)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) gr[a][j] = grad[(int64_t)(a * DIM + j) * N + idx];
+        viscous_flux<DIM>(ph, u, gr, Fv);
+    }
     Vec<NV> out;
     if constexpr (CART) {
         out.v[0] = qq[1 + m];
@@ -107,13 +123,20 @@ __device__ __forceinline__ void sat_point(const GridDev &g, const Phys &ph, cons
         double ri = 1.0 / qp[0];
 #pragma unroll
         for (int i = 0; i < DIM; ++i) u[i] = qp[1 + i] * ri;
-        double gr[DIM + 1][DIM];
-#pragma unroll
-        for (int a = 0; a <= DIM; ++a)
-#pragma unroll
-            for (int j = 0; j < DIM; ++j) gr[a][j] = grad[(int64_t)(a * DIM + j) * N + p];
         double Fv[DIM][DIM + 1];
-        viscous_flux<DIM>(ph, u, gr, Fv);
+        if constexpr (DIM == 3) {
+            double V[NVISC3];
+#pragma unroll
+            for (int k = 0; k < NVISC3; ++k) V[k] = grad[(int64_t)k * N + p];
+            viscous_flux3(u, V, Fv);
+        } else {
+            double gr[DIM + 1][DIM];
+#pragma unroll
+            for (int a = 0; a <= DIM; ++a)
+#pragma unroll
+                for (int j = 0; j < DIM; ++j) gr[a][j] = grad[(int64_t)(a * DIM + j) * N + p];
+            viscous_flux<DIM>(ph, u, gr, Fv);
+        }
         for (int m = 0; m < DIM; ++m) {
             int c = g.cls[m * N + p];
             int bc = (c >> 4) & 3;
@@ -322,10 +345,11 @@ __device__ __forceinline__ void tile3_origin(int tile, int ntx, int nty, int ntz
 // 3D Cartesian gradient pass on tiles: grad[(a*3+j)*N + p] = d(u, v, w, T)_a / dx_j
 // (zero at holes), the formulas of k_grad
 template <int SBP, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(TX * TY * TZ) k_grad_tile3d(GridDev g, double gm1, const double *__restrict__ q,
+__global__ void __launch_bounds__(TX * TY * TZ) k_grad_tile3d(GridDev g, Phys ph, const double *__restrict__ q,
                                                               double *__restrict__ grad, int ntx, int nty, int ntz,
                                                               int sy)
 {
+    const double gm1 = ph.gamma - 1.0;
     constexpr int R = SBP == 21 ? 1 : 3;
     using C = Tile3<TX, TY, TZ, R>;
     __shared__ double sW[4][C::RMAX];
@@ -404,10 +428,20 @@ __global__ void __launch_bounds__(TX * TY * TZ) k_grad_tile3d(GridDev g, double 
         __syncthreads();
     }
     if (!inside) return;
+    double V[NVISC3];
+    if (active) {
+        double gr[4][3];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) grad[(int64_t)(a * 3 + j) * N + p] = active ? g.inv_h[j] * dxi[j].v[a] : 0.0;
+            for (int j = 0; j < 3; ++j) gr[a][j] = g.inv_h[j] * dxi[j].v[a];
+        visc3_from_grad(ph, gr, V);
+    } else {
+#pragma unroll
+        for (int k = 0; k < NVISC3; ++k) V[k] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < NVISC3; ++k) grad[(int64_t)k * N + p] = V[k];
 }
 
 // 3D Cartesian flux divergence + SAT + AB on tiles, from the gradients of the
@@ -504,6 +538,221 @@ __global__ void __launch_bounds__(TX * TY * TZ) k_rhs_tile3d(GridDev g, Phys ph,
 #pragma unroll
         for (int v = 0; v < NV; ++v) r[v] = 0.0;
     }
+    store_step<3>(q, F, cb, N, p, r);
+}
+
+// coefficient of line offset o (|o| <= 3) in first-derivative row `row`: the
+// rows dsbp applies, as a table (row 15, a hole, has none)
+__constant__ double kRow42[9][7] = {
+    {0.0, 1.0 / 12.0, -2.0 / 3.0, 0.0, 2.0 / 3.0, -1.0 / 12.0, 0.0},
+    {0.0, 0.0, 0.0, C42_00, C42_01, C42_02, C42_03},
+    {0.0, 0.0, -0.5, 0.0, 0.5, 0.0, 0.0},
+    {0.0, C42_20, C42_21, 0.0, C42_23, C42_24, 0.0},
+    {C42_30, 0.0, C42_32, 0.0, C42_34, C42_35, 0.0},
+    {-C42_03, -C42_02, -C42_01, -C42_00, 0.0, 0.0, 0.0},
+    {0.0, 0.0, -0.5, 0.0, 0.5, 0.0, 0.0},
+    {0.0, -C42_24, -C42_23, 0.0, -C42_21, -C42_20, 0.0},
+    {0.0, -C42_35, -C42_34, 0.0, -C42_32, 0.0, -C42_30},
+};
+__constant__ double kRow21[3][3] = {{-0.5, 0.0, 0.5}, {0.0, -1.0, 1.0}, {-1.0, 1.0, 0.0}};
+
+template <int SBP>
+__device__ __forceinline__ double row_coef(int row, int o)
+{
+    if constexpr (SBP == 21)
+        return row <= 2 ? kRow21[row][o + 1] : 0.0;
+    else
+        return row <= 8 ? kRow42[row][o + 3] : 0.0;
+}
+
+// 3D Cartesian flux divergence and AB update, marching along z.  A workgroup
+// of TX x TY threads owns TX x TY point columns and a chunk of zc planes of
+// outputs (one output per thread and plane).  Per flux plane, each thread
+// evaluates the three directional fluxes of its own point once (from q and the
+// viscous quantities V of the gradient pass); the x and y fluxes of an output
+// plane go to LDS with the in-plane halo (2R columns along x, 2R rows along y,
+// one direction each, evaluated by the workgroup), the z flux is added at once,
+// scaled by its row coefficient, into the sums of the 2R + 1 output planes it
+// reaches (registers), which also receive their own plane's x and y
+// derivative sums.  Each flux is evaluated about 1 + 2R/TX + 2R/TY (x, y) and
+// 1 + 2R/zc (z) times per output.  SAT points are finished by k_sat3d, which
+// adds their penalties to the stored F and redoes their AB update.
+template <int SBP, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) k_rhs_zm3d(GridDev g, Phys ph, const double *__restrict__ q,
+                                                      const double *__restrict__ vis, double *__restrict__ F,
+                                                      Combine cb, int ntx, int nty, int nzc, int zc)
+{
+    constexpr int NV = 5, R = SBP == 21 ? 1 : 3, NT = TX * TY;
+    constexpr int EX = TX + 2 * R, EY = TY + 2 * R;
+    __shared__ double sX[NV][EX * TY];
+    __shared__ double sY[NV][TX * EY];
+    const int nblk = ntx * nty * nzc;
+    const int b = xcd_tile(blockIdx.x, nblk);
+    const int tx0 = (b % ntx) * TX, ty0 = ((b / ntx) % nty) * TY, z0 = (b / (ntx * nty)) * zc;
+    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
+    const int x = tx0 + lx, y = ty0 + ly;
+    const int64_t N = g.npts;
+    const bool col = x < g.n[0] && y < g.n[1];
+    const int zend = min(z0 + zc, g.n[2]);
+    const int nh = 2 * R * (TX + TY);
+    const int64_t pc = col ? x * g.stride[0] + y * g.stride[1] : 0;   // column base
+
+    // flux of direction m at in-plane point (i, j) of plane k (zero off the
+    // grid and at holes); periodic directions wrap
+    auto flux_at = [&](int i, int j, int k, int m) -> Vec<NV> {
+        Vec<NV> f;
+        const int c[3] = {i, j, k};
+        int64_t idx = 0;
+        bool ok = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int v = c[d];
+            if (g.periodic[d]) v = v < 0 ? v + g.n[d] : (v >= g.n[d] ? v - g.n[d] : v);
+            ok = ok && v >= 0 && v < g.n[d];
+            idx += (int64_t)v * g.stride[d];
+        }
+        ok = ok && (g.cls[idx] & 15) != CLS_HOLE;
+        if (ok) {
+            f = fhat_at<3, 1>(g, ph, q, vis, m, idx);
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) f.v[v] = 0.0;
+        }
+        return f;
+    };
+    // plane index inside the grid (periodic wrap), -1 off the grid
+    auto plane = [&](int k) -> int {
+        if (g.periodic[2]) k = k < 0 ? k + g.n[2] : (k >= g.n[2] ? k - g.n[2] : k);
+        return k >= 0 && k < g.n[2] ? k : -1;
+    };
+
+    // acc[e]: sums of output plane k - R + e (e = 0 completes at flux plane k);
+    // rz[e]: its z row
+    Vec<NV> acc[2 * R + 1];
+    int rz[2 * R + 1];
+#pragma unroll
+    for (int e = 0; e <= 2 * R; ++e) {
+        rz[e] = CLS_HOLE;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[e].v[v] = 0.0;
+    }
+    const int nplanes = (zend - z0) + 2 * R;
+    for (int s = 0; s < nplanes; ++s) {
+        const int k = z0 - R + s;                 // flux plane
+        const bool outp = k >= z0 && k < zend;    // an output plane of the chunk (uniform)
+        // open the slot of output plane k + R
+#pragma unroll
+        for (int e = 0; e < 2 * R; ++e) {
+            acc[e] = acc[e + 1];
+            rz[e] = rz[e + 1];
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[2 * R].v[v] = 0.0;
+        {
+            const int oz = k + R;
+            rz[2 * R] = col && oz < zend ? g.cls[2 * N + pc + (int64_t)oz * g.stride[2]] & 15 : CLS_HOLE;
+        }
+        const int kw = plane(k);
+        const int64_t p = pc + (int64_t)(kw < 0 ? 0 : kw) * g.stride[2];
+        const bool act = col && kw >= 0 && (g.cls[p] & 15) != CLS_HOLE;
+        Vec<NV> own[3];
+        if (act) {
+            if (outp) {
+                fluxes3(g, ph, q, vis, p, own);
+            } else {
+                own[2] = fhat_at<3, 1>(g, ph, q, vis, 2, p);
+            }
+            // z flux into the sums of the output planes it reaches
+#pragma unroll
+            for (int e = 0; e <= 2 * R; ++e) {
+                const double c = row_coef<SBP>(rz[e], R - e) * g.inv_h[2];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) acc[e].v[v] += c * own[2].v[v];
+            }
+        }
+        if (outp) {
+            if (col) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    sX[v][(lx + R) + EX * ly] = act ? own[0].v[v] : 0.0;
+                    sY[v][lx + TX * (ly + R)] = act ? own[1].v[v] : 0.0;
+                }
+            } else {
+                // a column past the grid's end (partial tile): the wrapped
+                // point of a periodic direction, zero otherwise
+                Vec<NV> fx = flux_at(x, y, k, 0), fy = flux_at(x, y, k, 1);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    sX[v][(lx + R) + EX * ly] = fx.v[v];
+                    sY[v][lx + TX * (ly + R)] = fy.v[v];
+                }
+            }
+            for (int h = tid; h < nh; h += NT) {
+                if (h < 2 * R * TY) {
+                    const int sd = h % (2 * R), r = h / (2 * R);
+                    const int ex = sd < R ? sd : sd + TX;
+                    Vec<NV> f = flux_at(tx0 + ex - R, ty0 + r, k, 0);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) sX[v][ex + EX * r] = f.v[v];
+                } else {
+                    const int h2 = h - 2 * R * TY;
+                    const int c = h2 % TX, sd = h2 / TX;
+                    const int ey = sd < R ? sd : sd + TY;
+                    Vec<NV> f = flux_at(tx0 + c, ty0 + ey - R, k, 1);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) sY[v][c + TX * ey] = f.v[v];
+                }
+            }
+            __syncthreads();
+            if (act) {
+                Vec<NV> dx = dsbp<SBP, NV>(g.cls[p] & 15, [&](int o) {
+                    Vec<NV> r;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) r.v[v] = sX[v][(lx + R + o) + EX * ly];
+                    return r;
+                });
+                Vec<NV> dy = dsbp<SBP, NV>(g.cls[N + p] & 15, [&](int o) {
+                    Vec<NV> r;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) r.v[v] = sY[v][lx + TX * (ly + R + o)];
+                    return r;
+                });
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    double a = acc[R].v[v];
+                    a += g.inv_h[0] * dx.v[v];
+                    a += g.inv_h[1] * dy.v[v];
+                    acc[R].v[v] = a;
+                }
+            }
+            __syncthreads();
+        }
+        // output plane k - R is complete
+        const int oz = k - R;
+        if (oz >= z0 && col) {
+            const int64_t po = pc + (int64_t)oz * g.stride[2];
+            double r[NV];
+            const bool oact = rz[0] != CLS_HOLE;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) r[v] = oact ? -1.0 * acc[0].v[v] : 0.0;
+            store_step<3>(q, F, cb, N, po, r);
+        }
+    }
+}
+
+// SAT points of a 3D grid after k_rhs_zm3d: F holds the flux-divergence part;
+// add the penalties, store F and redo the AB update
+__global__ void __launch_bounds__(256) k_sat3d(GridDev g, Phys ph, const double *__restrict__ q,
+                                               const double *__restrict__ vis, double *__restrict__ F, Combine cb,
+                                               const int32_t *__restrict__ pts, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t N = g.npts, p = pts[i];
+    double r[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) r[v] = F[v * N + p];
+    sat_point<3, 1>(g, ph, q, vis, p, r);
     store_step<3>(q, F, cb, N, p, r);
 }
 
@@ -1528,9 +1777,23 @@ hipError_t launch_rhs_tile2d_donor(const GridDev &g, int sbp, const Phys &ph, co
 }
 
 #define DISPATCH_GRAD(DIM, SBP, CART) \
-    hipLaunchKernelGGL((k_grad<DIM, SBP, CART>), dim3(nblk(g.npts, 256)), dim3(256), 0, st, g, gm1, q, grad)
+    hipLaunchKernelGGL((k_grad<DIM, SBP, CART>), dim3(nblk(g.npts, 256)), dim3(256), 0, st, g, ph, q, grad)
 
 const TileShape3 kTile3dShapes[NUM_TILE3D_SHAPES] = {{8, 8, 8}, {16, 8, 4}, {32, 4, 4}, {16, 4, 4}};
+
+template <int TX, int TY, int TZ>
+static hipError_t grad3d_shape(const GridDev &g, int sbp, const Phys &ph, const double *q, double *vis, int slab,
+                               hipStream_t st)
+{
+    const int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY, ntz = (g.n[2] + TZ - 1) / TZ;
+    const int sy = slab > 0 && slab < nty ? slab : nty;
+    const dim3 grid((unsigned)(ntx * nty * ntz)), block(TX * TY * TZ);
+    if (sbp == 21)
+        hipLaunchKernelGGL((k_grad_tile3d<21, TX, TY, TZ>), grid, block, 0, st, g, ph, q, vis, ntx, nty, ntz, sy);
+    else
+        hipLaunchKernelGGL((k_grad_tile3d<42, TX, TY, TZ>), grid, block, 0, st, g, ph, q, vis, ntx, nty, ntz, sy);
+    return hipGetLastError();
+}
 
 template <int TX, int TY, int TZ>
 static hipError_t tile3d_shape(const GridDev &g, int sbp, const Phys &ph, const double *q, double *grad,
@@ -1539,18 +1802,62 @@ static hipError_t tile3d_shape(const GridDev &g, int sbp, const Phys &ph, const 
     const int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY, ntz = (g.n[2] + TZ - 1) / TZ;
     const int sy = slab > 0 && slab < nty ? slab : nty;
     const dim3 grid((unsigned)(ntx * nty * ntz)), block(TX * TY * TZ);
-    const double gm1 = ph.gamma - 1.0;
     double *gw = grad;
     if (sbp == 21) {
-        hipLaunchKernelGGL((k_grad_tile3d<21, TX, TY, TZ>), grid, block, 0, st, g, gm1, q, gw, ntx, nty, ntz, sy);
+        hipLaunchKernelGGL((k_grad_tile3d<21, TX, TY, TZ>), grid, block, 0, st, g, ph, q, gw, ntx, nty, ntz, sy);
         hipLaunchKernelGGL((k_rhs_tile3d<21, TX, TY, TZ>), grid, block, 0, st, g, ph, q, grad, F, cb, ntx, nty, ntz,
                            sy);
     } else {
-        hipLaunchKernelGGL((k_grad_tile3d<42, TX, TY, TZ>), grid, block, 0, st, g, gm1, q, gw, ntx, nty, ntz, sy);
+        hipLaunchKernelGGL((k_grad_tile3d<42, TX, TY, TZ>), grid, block, 0, st, g, ph, q, gw, ntx, nty, ntz, sy);
         hipLaunchKernelGGL((k_rhs_tile3d<42, TX, TY, TZ>), grid, block, 0, st, g, ph, q, grad, F, cb, ntx, nty, ntz,
                            sy);
     }
     return hipGetLastError();
+}
+
+template <int TX, int TY>
+static hipError_t zm3d_shape(const GridDev &g, int sbp, const Phys &ph, const double *q, const double *vis,
+                             double *F, const Combine &cb, int zc, const int32_t *satpts, int nsat, hipStream_t st)
+{
+    const int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY;
+    if (zc <= 0) {
+        // about 768 workgroups (three per CU), chunks of at least 16 planes
+        int nz = (768 + ntx * nty - 1) / (ntx * nty);
+        nz = max(1, min(nz, g.n[2] / 16));
+        zc = (g.n[2] + nz - 1) / nz;
+    }
+    const int nzc = (g.n[2] + zc - 1) / zc;
+    const dim3 grid((unsigned)(ntx * nty * nzc)), block(TX * TY);
+    if (sbp == 21)
+        hipLaunchKernelGGL((k_rhs_zm3d<21, TX, TY>), grid, block, 0, st, g, ph, q, vis, F, cb, ntx, nty, nzc, zc);
+    else
+        hipLaunchKernelGGL((k_rhs_zm3d<42, TX, TY>), grid, block, 0, st, g, ph, q, vis, F, cb, ntx, nty, nzc, zc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nsat == 0) return e;
+    hipLaunchKernelGGL(k_sat3d, dim3(nblk(nsat, 256)), dim3(256), 0, st, g, ph, q, vis, F, cb, satpts, nsat);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_zm3d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *vis, double *F,
+                           const Combine &cb, int grad_shape, int slab, int shape, int zc, const int32_t *satpts,
+                           int nsat, hipStream_t st)
+{
+    if (g.dim != 3 || !g.cartesian || (sbp != 21 && sbp != 42)) return hipErrorInvalidValue;
+    hipError_t e;
+    switch (grad_shape) {
+    case 0: e = grad3d_shape<8, 8, 8>(g, sbp, ph, q, vis, slab, st); break;
+    case 1: e = grad3d_shape<16, 8, 4>(g, sbp, ph, q, vis, slab, st); break;
+    case 2: e = grad3d_shape<32, 4, 4>(g, sbp, ph, q, vis, slab, st); break;
+    case 3: e = grad3d_shape<16, 4, 4>(g, sbp, ph, q, vis, slab, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    switch (shape) {
+    case 1: return zm3d_shape<16, 16>(g, sbp, ph, q, vis, F, cb, zc, satpts, nsat, st);
+    case 2: return zm3d_shape<32, 8>(g, sbp, ph, q, vis, F, cb, zc, satpts, nsat, st);
+    case 3: return zm3d_shape<16, 8>(g, sbp, ph, q, vis, F, cb, zc, satpts, nsat, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_rhs_tile3d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *grad,
@@ -1566,7 +1873,7 @@ hipError_t launch_rhs_tile3d(const GridDev &g, int sbp, const Phys &ph, const do
     }
 }
 
-hipError_t launch_grad(const GridDev &g, int sbp, double gm1, const double *q, double *grad, hipStream_t st)
+hipError_t launch_grad(const GridDev &g, int sbp, const Phys &ph, const double *q, double *grad, hipStream_t st)
 {
     if (g.dim == 2 && sbp == 21 && g.cartesian) DISPATCH_GRAD(2, 21, 1);
     else if (g.dim == 2 && sbp == 21) DISPATCH_GRAD(2, 21, 0);

@@ -54,6 +54,8 @@ struct GridHost {
     // states at the points its donor stencils read, one buffer per mid-step
     std::vector<int32_t> closure;     // sorted donor-stencil points
     int32_t *closure_d = nullptr;
+    std::vector<int32_t> satpts;      // 3D: active points ending a run in some direction (SAT points)
+    int32_t *satpts_d = nullptr;
     std::vector<double *> ext;        // per mid-step offset jp = 1..per-1
 };
 
@@ -149,6 +151,8 @@ struct mr_ctx {
     bool ride_donors = true;  // one stream: mid-step donor data in the next same-time 2D evaluation's launch
     int tile3d = 1;           // 3D passes: LDS tile shape (mrk::kTile3dShapes), -1 the per-point kernels
     int slab3d = 3;           // 3D passes: tile rows per slab of the tile order (0: plain x, y, z order)
+    int flux3d = 0;           // 3D flux pass: 0 on tiles, 1..3 marching along z (columns 16x16, 32x8, 16x8)
+    int zchunk3d = 0;         // 3D z-marching flux pass: planes per chunk (0: from the grid size)
     int period = 1;                            // macrosteps after which every pointer repeats
     int64_t version = 0;                       // bumped when a batch's launch plan must be rebuilt
     // macrosteps: one stream per grid, ordered by events (Order); -1: when
@@ -510,7 +514,7 @@ size_t layout(mr_ctx *c, char *base)
         g.y[0] = cv.take<double>((size_t)nv * N);
         g.y[1] = cv.take<double>((size_t)nv * N);
         g.hist = cv.take<double>((size_t)m * nv * N);
-        g.grad = cv.take<double>((size_t)g.dim * (g.dim + 1) * N);
+        g.grad = cv.take<double>((size_t)(g.dim == 3 ? mrk::NVISC3 : g.dim * (g.dim + 1)) * N);
         for (int k = 0; k < 5; ++k) g.rk[k] = cv.take<double>((size_t)nv * N);
         g.dt = cv.take<double>((size_t)N);
         g.cls_d = cv.take<int8_t>((size_t)g.dim * N);
@@ -523,6 +527,7 @@ size_t layout(mr_ctx *c, char *base)
         g.ext.assign(per > 1 && !g.closure.empty() ? per - 1 : 0, nullptr);
         for (auto &e : g.ext) e = cv.take<double>((size_t)nv * N);
         g.closure_d = g.closure.empty() ? nullptr : cv.take<int32_t>(g.closure.size());
+        g.satpts_d = g.satpts.empty() ? nullptr : cv.take<int32_t>(g.satpts.size());
     }
     size_t R = c->rgrid.size();
     c->euid_d = cv.take<int32_t>(R * c->S + 1);
@@ -843,10 +848,13 @@ int grid_rhs(mr_ctx *c, int gi, const double *q, double *F, const mrk::Combine &
     } else if (g.dim == 2 && !c->two_pass) {
         int shape = g.tile >= 0 ? g.tile : mrk::default_tile_shape(dev);
         HIPCHK(c, mrk::launch_rhs_tile2d(dev, c->P.sbp, c->ph, q, F, cb, shape, st));
+    } else if (g.dim == 3 && c->tile3d >= 0 && c->flux3d > 0) {
+        HIPCHK(c, mrk::launch_rhs_zm3d(dev, c->P.sbp, c->ph, q, g.grad, F, cb, c->tile3d, c->slab3d, c->flux3d,
+                                       c->zchunk3d, g.satpts_d, (int)g.satpts.size(), st));
     } else if (g.dim == 3 && c->tile3d >= 0) {
         HIPCHK(c, mrk::launch_rhs_tile3d(dev, c->P.sbp, c->ph, q, g.grad, F, cb, c->tile3d, c->slab3d, st));
     } else {
-        HIPCHK(c, mrk::launch_grad(dev, c->P.sbp, c->P.gamma - 1.0, q, g.grad, st));
+        HIPCHK(c, mrk::launch_grad(dev, c->P.sbp, c->ph, q, g.grad, st));
         HIPCHK(c, mrk::launch_rhs(dev, c->grids_d + gi, c->P.sbp, c->ph, q, g.grad, F, cb, st));
     }
     if (rec) {
@@ -2270,6 +2278,16 @@ int mr_finalize(mr_ctx *c, size_t *bytes)
     }
     for (size_t g = 0; g < c->G.size(); ++g)
         if (c->G[g].rate < c->rmax) build_closure(c, (int)g, c->G[g]);
+    for (auto &g : c->G) {
+        g.satpts.clear();
+        if (g.dim != 3) continue;
+        for (int64_t p = 0; p < g.npts; ++p) {
+            if ((g.cls[p] & 15) == mrk::CLS_HOLE) continue;
+            bool any = false;
+            for (int d = 0; d < g.dim; ++d) any = any || ((g.cls[(size_t)d * g.npts + p] >> 4) & 3) != 0;
+            if (any) g.satpts.push_back((int32_t)p);
+        }
+    }
     c->euid.assign(c->ept.size(), 0);
     for (Link &L : c->links) {
         size_t e0 = (size_t)L.first * c->S, e1 = (size_t)(L.first + L.n) * c->S;
@@ -2305,6 +2323,9 @@ int bind_at(mr_ctx *c, void *dev)
                                      c->st));
         if (!g.closure.empty())
             HIPCHK(c, hipMemcpyAsync(g.closure_d, g.closure.data(), g.closure.size() * 4, hipMemcpyHostToDevice,
+                                     c->st));
+        if (!g.satpts.empty())
+            HIPCHK(c, hipMemcpyAsync(g.satpts_d, g.satpts.data(), g.satpts.size() * 4, hipMemcpyHostToDevice,
                                      c->st));
         GridDev &D = g.dev;
         D.dim = g.dim;
@@ -2786,6 +2807,12 @@ int mr_set_option(mr_ctx *c, const char *name, int64_t value)
         if (value < -1 || value >= mrk::NUM_TILE3D_SHAPES)
             return fail(c, MR_ERR_ARG, "rhs_tile3d must be -1 .. %d", mrk::NUM_TILE3D_SHAPES - 1);
         c->tile3d = (int)value;
+    } else if (!strcmp(name, "flux3d")) {
+        if (value < 0 || value > 3) return fail(c, MR_ERR_ARG, "flux3d must be 0 .. 3");
+        c->flux3d = (int)value;
+    } else if (!strcmp(name, "zchunk3d")) {
+        if (value < 0 || value > 4096) return fail(c, MR_ERR_ARG, "zchunk3d must be 0 .. 4096");
+        c->zchunk3d = (int)value;
     } else if (!strcmp(name, "ride_donors")) {
         if (value != 0 && value != 1) return fail(c, MR_ERR_ARG, "ride_donors must be 0 or 1");
         c->ride_donors = value == 1;

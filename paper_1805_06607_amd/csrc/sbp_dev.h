@@ -172,6 +172,49 @@ __device__ __forceinline__ void viscous_flux(const Phys &ph, const double *u, do
     }
 }
 
+// 3D: V layout (NVISC3 values per point, kern.h): tau_00, tau_11, tau_22,
+// tau_01, tau_02, tau_12, then h_0, h_1, h_2
+__device__ __forceinline__ int visc3_tau(int i, int j)
+{
+    return i == j ? i : (i + j == 1 ? 3 : (i + j == 2 ? 4 : 5));
+}
+
+// V of a point from its gradients, the arithmetic of viscous_flux<3>
+__device__ __forceinline__ void visc3_from_grad(const Phys &ph, double gr[4][3], double *V)
+{
+    double mre = ph.mu / ph.Re, lre = ph.lam / ph.Re;
+    double kc = ph.mu * ph.gamma / ((ph.gamma - 1.0) * ph.Re * ph.Pr);
+    double div = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) div += gr[i][i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j) {
+            double tau = mre * (gr[i][j] + gr[j][i]);
+            if (i == j) tau += lre * div;
+            V[visc3_tau(i, j)] = tau;
+        }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) V[6 + j] = kc * gr[3][j];
+}
+
+// Cartesian viscous flux vectors (components 1..4) of a 3D point from V
+__device__ __forceinline__ void viscous_flux3(const double *u, const double *V, double Fv[3][4])
+{
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        double w = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            double tau = V[visc3_tau(i, j)];
+            Fv[j][i] = tau;
+            w += u[i] * tau;
+        }
+        Fv[j][3] = w + V[6 + j];
+    }
+}
+
 // --------------------------------------------------------- SAT (closed form)
 // K^{+-} dQ for the Euler flux Jacobian along the (non-normalised) direction
 // n, at state q, via characteristic wave strengths (entropy + shear waves at

@@ -30,10 +30,15 @@ def small():
     return workloads.tgv3d(nbg=48, npatch=24, ninner=16)
 
 
-@pytest.mark.parametrize("tile3d", [-1, 0, 1, 2, 3])
-def test_rhs_parity_3d(torch, tile3d):
-    """Point-wise flux kernel (-1) and every LDS tile shape of the 3D flux
-    pass (the 32-wide and 4-deep tiles leave partial tiles on these grids)."""
+@pytest.mark.parametrize("tile3d,flux3d,zchunk", [
+    (-1, 0, 0), (0, 0, 0), (1, 0, 0), (2, 0, 0), (3, 0, 0),
+    (1, 1, 0), (1, 2, 0), (1, 3, 0), (0, 1, 5), (1, 1, 7), (2, 2, 13), (3, 3, 48)])
+def test_rhs_parity_3d(torch, tile3d, flux3d, zchunk):
+    """Point-wise flux kernel (-1), every LDS tile shape of the gradient and
+    flux passes, and the z-marching flux pass on every column shape with
+    chunks of planes that leave a shorter last chunk (5, 7, 13) or hold a
+    whole grid (48); the 32-wide and 4-deep tiles leave partial tiles on
+    these grids."""
     from oracle import OracleSystem
     from paper_1805_06607_amd.system import System
     wl = small()
@@ -42,13 +47,40 @@ def test_rhs_parity_3d(torch, tile3d):
     want = orc.rhs(states)
     sysg = System(wl)
     sysg.set_option("rhs_tile3d", tile3d)
+    sysg.set_option("flux3d", flux3d)
+    sysg.set_option("zchunk3d", zchunk)
     got = sysg.rhs(states)
     for g in range(len(wl.grids)):
         act = orc.grids[g].iblank.astype(bool)
         e = rel_l2(_np(got[g]), want[g], act)
-        _say("3d rhs", tile3d, g, e)
+        _say("3d rhs", tile3d, flux3d, zchunk, g, e)
         assert np.all(e <= 1e-12), (g, e)
         assert np.all(_np(got[g])[:, ~act] == 0.0)
+
+
+def test_zmarch_over_shapes_and_chunks(torch):
+    """The z-marching flux pass evaluates every flux and every sum by the same
+    formulas whatever its column shape and chunk length (a flux evaluated for
+    a thread's own point or for a halo point may differ in its last bit,
+    where the compiler contracts a multiply-add differently in one place):
+    states equal to 1e-11 after 6 macrosteps (w starts at zero, so its
+    momentum is small and its relative error the largest)."""
+    from paper_1805_06607_amd.system import System
+    outs = []
+    for flux3d, zchunk in ((1, 0), (2, 0), (3, 0), (1, 5), (2, 11), (3, 48)):
+        wl = small()
+        s = System(wl)
+        s.set_option("flux3d", flux3d)
+        s.set_option("zchunk3d", zchunk)
+        s.timestep()
+        s.start(0.0)
+        s.macrostep(6)
+        outs.append([s.state(g).clone() for g in range(len(wl.grids))])
+        _say("zmarch", flux3d, zchunk, "done")
+    for o in outs[1:]:
+        for g in range(len(o)):
+            e = rel_l2(_np(o[g]), _np(outs[0][g]))
+            assert np.all(e <= 1e-11), (g, e)
 
 
 def test_receiver_data_parity_3d(torch):
