@@ -237,3 +237,24 @@ def test_full_size_freestream_3d(torch, full3d):
         d = np.abs(_np(sysg.state(g))[:, act] - q[:, None]).max(axis=1) / np.abs(q)
         _say("full 3d free stream", g, d)
         assert np.all(d <= 1e-12), (g, d)
+
+
+def test_full_size_multi_stream_bitwise_3d(torch, full3d):
+    """Full-size 3D case, seeded non-uniform state (the Taylor-Green field
+    with a 1e-3 random perturbation): 6 macrosteps on per-grid streams (the
+    bench's plan at this size) are bitwise those of the single-stream order."""
+    wl, sysg = full3d
+    states = workloads.random_state_like(wl, seed=13, amp=1e-3)
+    outs = []
+    for ms in (0, 1):
+        sysg.set_option("multi_stream", ms)
+        sysg.set_states(states)
+        sysg.timestep()
+        sysg.start(0.0)
+        for n in (2, 4):
+            sysg.macrostep(n)
+        outs.append([sysg.state(g).clone() for g in range(len(wl.grids))])
+        _say("full 3d multi_stream", ms, "done")
+    for g, (a, b) in enumerate(zip(*outs)):
+        assert torch.isfinite(a).all(), g
+        assert torch.equal(a, b), g
