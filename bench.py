@@ -15,13 +15,15 @@ right-hand side, SAT and AB update for every evaluating grid).  The timed
 region holds exactly K macrosteps with the states already in device memory.
 value = MRAB point-updates per second = sum_l r_l * N_l(active) * K / time.
 
-Also reported: the single-rate AB (every grid at the fast step) rate, the
-errors of both against a single-rate reference at a 4x smaller step (equal
-error check), the roofline of the dominant kernel (the fused right-hand-side
-step of every grid, each launch timed with HIP events on the stream it runs on
-inside the timed region; HBM traffic per launch from the committed counter
-summary when it matches the kernels' source), and the CPU oracle on a bounded
-sample.
+Also reported: the single-rate AB (every grid at the fast step) rate; the
+equal-error comparison of both against a single-rate reference at a 32x
+smaller step; the 3D three-level case (192^3 background, two 96^3 patches, a
+64^3 patch; rates 1, 2, 2, 4), whose right-hand-side pass pair is the
+HBM-bound kernel and gives the line's "roofline" (each launch timed with HIP
+events on the stream it runs on, next to the kernel-trace durations and the
+HBM traffic per launch of the committed profiles when they match the kernels'
+source; the cylinder's fused kernel is "roofline_cylinder"); and the CPU oracle
+on bounded samples of both workloads, on every host core and on one.
 """
 import argparse
 import json
@@ -48,10 +50,17 @@ def workload(rates=(1, 4)):
     return wl
 
 
-def run_tgv3d(args):
-    """Secondary mode: the 3D three-level case (192^3 background, two 96^3
-    patches, one 64^3 patch; rates 1, 2, 2, 4; SBP 4-2, AB3) -- the
-    HBM-bound configuration.  Prints one JSON line of its own."""
+TGV3D_WORKLOAD = ("3D periodic 192^3 + 2 x 96^3 (half spacing) + 64^3 (quarter spacing), SBP 4-2, cubic donors, "
+                  "AB3, rates 1/2/2/4, Re 1600, M 0.3")
+
+
+def tgv3d_measure(args):
+    """The 3D three-level case (192^3 background, two 96^3 patches, one 64^3
+    patch; rates 1, 2, 2, 4; SBP 4-2, AB3) -- the HBM-bound configuration:
+    MRAB pt-updates/s over K macrosteps (per-grid streams, the library's
+    plan at this size), then the roofline of the right-hand-side pass pair
+    from a single-stream pass of K macrosteps with every launch between HIP
+    events, next to the kernel-trace durations of the committed profile."""
     import torch
     import workloads
     from paper_1805_06607_amd.system import System
@@ -69,19 +78,32 @@ def run_tgv3d(args):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     s.guard()
+    log(f"3D MRAB {args.steps} macrosteps: {el * 1e3:.2f} ms")
     # launch durations from a single-stream pass (on the per-grid streams the
     # grids' launches overlap and each event pair would also time the others)
     s.set_option("multi_stream", 0)
     roof = timed_pass(s, wl, n_act, args.steps, "gradient pass + flux divergence, SAT and fused AB update on "
                                                 "LDS tiles (k_grad_tile3d + k_rhs_tile3d), all grids' launches "
                                                 "of a macrostep")
-    line = {"metric": "MRAB pt-updates/s (3D three-level case), 1 GPU", "value": pts * args.steps / el,
+    roof["workload"] = TGV3D_WORKLOAD
+    s.close()
+    return {"value": pts * args.steps / el, "unit": "pt-updates/s", "ms_per_step": el / args.steps * 1e3,
+            "steps": args.steps, "points_active": n_act, "rates": [g.rate for g in wl.grids], "H": H,
+            "roofline": roof, "_wl": wl}
+
+
+def run_tgv3d(args):
+    """Secondary mode: the 3D case alone.  Prints one JSON line of its own."""
+    r = tgv3d_measure(args)
+    wl = r.pop("_wl")
+    line = {"metric": "MRAB pt-updates/s (3D three-level case), 1 GPU", "value": r["value"],
             "unit": "pt-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-            "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": "3D periodic 192^3 + 2 x 96^3 (half spacing) + 64^3 (quarter spacing), "
-                                   "SBP 4-2, cubic donors, AB3, rates 1/2/2/4, Re 1600, M 0.3",
-                       "points_active": n_act, "H": H},
-            "roofline": roof}
+            "ms_per_step": r["ms_per_step"], "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": TGV3D_WORKLOAD, "points_active": r["points_active"], "H": r["H"]},
+            "roofline": r["roofline"]}
+    if not args.no_cpu:
+        log("cpu baseline (3D)")
+        line["cpu_baseline"] = cpu_baseline_3d(args, wl)
     print(json.dumps(line), flush=True)
 
 
@@ -305,24 +327,54 @@ TILE3D = (16, 8, 4)   # the 3D passes' default LDS tile (option rhs_tile3d = 1)
 
 
 def kernel_names(sysg, wl):
-    """Key of each grid's right-hand-side launches in the counter summary:
-    the fused 2D kernel's instantiation, or for 3D the gradient + flux pass
-    pair by its launch size (threads)."""
+    """Per grid: the key of its right-hand-side launches in the counter
+    summary (the fused 2D kernel's instantiation, or for 3D the gradient +
+    flux pass pair by its launch size in threads) and the kernel-trace keys
+    (instantiation and launch size) of the launches one step makes."""
     names = []
+    sbp = int(wl.params["sbp"])
     if wl.dim == 3:
+        tile = "{}, {}, {}".format(*TILE3D)
         for gr in wl.grids:
             threads = 1
             for n, t in zip(gr.n, TILE3D):
                 threads *= -(-n // t) * t
-            names.append(f"tile3d_pair grid={threads}")
+            names.append((f"tile3d_pair grid={threads}",
+                          [f"k_grad_tile3d<{sbp}, {tile}> grid={threads}",
+                           f"k_rhs_tile3d<{sbp}, {tile}> grid={threads}"]))
         return names
     for g, gr in enumerate(wl.grids):
         shape, tx, ty, tm = sysg.tile_shape(g)
         if shape < 0:
-            names.append(None)
+            names.append((None, []))
             continue
-        names.append(f"k_rhs_tile2d<{int(wl.params['sbp'])}, {0 if gr.kind == 1 else 1}, {tx}, {ty}, {tm}>")
+        k = f"k_rhs_tile2d<{sbp}, {0 if gr.kind == 1 else 1}, {tx}, {ty}, {tm}>"
+        threads = (-(-gr.n[0] // tx)) * (-(-gr.n[1] // ty)) * tx * ty * tm
+        names.append((k, [f"{k} grid={threads}"]))
     return names
+
+
+def stored_trace():
+    """Average kernel durations [us] from the committed kernel-trace summary,
+    keyed 'instantiation grid=threads', if it was taken on the kernels as they
+    are now (same source hash)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "kernel_trace.txt")
+    src = os.path.join(ROOT, "paper_1805_06607_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return {}
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    out, ok = {}, False
+    with open(path) as f:
+        for ln in f:
+            ln = ln.strip()
+            if ln.startswith("kernels_sha256"):
+                ok = ln.split("=", 1)[1].strip() == sha
+            elif ln.startswith("k_") and " avg_us=" in ln:
+                key, val = ln.rsplit(" avg_us=", 1)
+                out[key.strip()] = float(val)
+    return out if ok else {}
 
 
 def stored_traffic():
@@ -365,11 +417,16 @@ def timed_pass(sysg, wl, n_act, steps, what):
 def roofline(sysg, wl, n_act, what):
     """Roofline of the fused right-hand-side step over every timed launch of
     the timed region: algorithmic bytes (bytes_per_point x active points per
-    launch) / summed launch duration, and per grid."""
+    launch) / summed launch duration, and per grid.  Next to the event-timed
+    durations (which include each launch's dispatch latency): the kernel-trace
+    durations of the committed profile, when it was taken on the kernels as
+    they are now."""
     per_grid, tb, tt, tn = [], 0.0, 0.0, 0
     names = kernel_names(sysg, wl)
     traffic = stored_traffic()
+    trace = stored_trace()
     tr_bytes, tr_ok = 0.0, True
+    kt_time, kt_ok = 0.0, True
     for g in range(len(wl.grids)):
         ms, cnt = sysg.kernel_time(g)
         if cnt == 0:
@@ -378,12 +435,21 @@ def roofline(sysg, wl, n_act, what):
         bl = n_act[g] * bpp
         avg = ms * 1e-3 / cnt
         ach = bl / avg / 1e9
-        d = {"grid": g, "n": list(wl.grids[g].n), "kernel": names[g], "points": n_act[g], "bytes_per_point": bpp,
+        key, launches = names[g]
+        d = {"grid": g, "n": list(wl.grids[g].n), "kernel": key, "points": n_act[g], "bytes_per_point": bpp,
              "bytes_per_launch": bl, "launches": cnt, "avg_launch_us": avg * 1e6, "achieved": ach,
              "frac": ach / HBM_PEAK_GBS}
-        if names[g] in traffic:
-            d["traffic"] = traffic[names[g]]
-            tr_bytes += traffic[names[g]] * cnt
+        if all(k in trace for k in launches):
+            kt = sum(trace[k] for k in launches)
+            d["kernel_trace_us"] = kt
+            d["kernel_trace_launches"] = launches
+            d["frac_kernel_trace"] = bl / (kt * 1e-6) / 1e9 / HBM_PEAK_GBS
+            kt_time += kt * 1e-6 * cnt
+        else:
+            kt_ok = False
+        if key in traffic:
+            d["traffic"] = traffic[key]
+            tr_bytes += traffic[key] * cnt
         else:
             tr_ok = False
         per_grid.append(d)
@@ -391,10 +457,16 @@ def roofline(sysg, wl, n_act, what):
         tt += ms * 1e-3
         tn += cnt
     ach = tb / tt / 1e9
-    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-            "traffic": (tr_bytes / tn) if (tr_ok and tn) else None, "kernel": what,
-            "bytes_per_launch": tb / tn, "avg_launch_us": tt / tn * 1e6, "launches_timed": tn,
-            "per_grid": per_grid}
+    out = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+           "traffic": (tr_bytes / tn) if (tr_ok and tn) else None, "kernel": what,
+           "bytes_per_launch": tb / tn, "avg_launch_us": tt / tn * 1e6, "launches_timed": tn,
+           "timing": "HIP events around each launch on its stream (includes dispatch latency)"}
+    if kt_ok and tn:
+        out["kernel_trace_avg_launch_us"] = kt_time / tn * 1e6
+        out["frac_kernel_trace"] = tb / kt_time / 1e9 / HBM_PEAK_GBS
+        out["kernel_trace_source"] = "profiles/kernel_trace.txt"
+    out["per_grid"] = per_grid
+    return out
 
 
 def active_counts(sysg):
@@ -445,9 +517,9 @@ def run_gpu(args):
     # macrosteps identical to the timed one, each launch between HIP events
     # (the events themselves cost host time, so the throughput above is taken
     # without them)
-    res["roofline"] = timed_pass(mr, wl, n_act, args.steps,
-                                 "k_rhs_tile2d (fused gradients, flux divergence, SAT, AB update), "
-                                 "all launches of a macrostep (background and O-mesh)")
+    res["roofline_cylinder"] = timed_pass(mr, wl, n_act, args.steps,
+                                          "k_rhs_tile2d (fused gradients, flux divergence, SAT, AB update), "
+                                          "all launches of a macrostep (background and O-mesh)")
     del mr
     # ---------------------------------------------------------------- SRAB
     wls = workload((1, 1))
@@ -471,19 +543,38 @@ def run_gpu(args):
     # -------------------------------------------------------- equal error
     if not args.no_equal_error:
         res["equal_error"] = equal_error(args, h)
+    # ------------------------------------ 3D case: the HBM roofline config
+    if not args.no_3d:
+        res["tgv3d"] = tgv3d_measure(args3d(args))
+        res["roofline"] = res["tgv3d"]["roofline"]
+    else:
+        res["roofline"] = res["roofline_cylinder"]
     return res, wl, n_act
 
 
+def args3d(args):
+    """The 3D part of the default run: K = max(5, steps / 20) macrosteps
+    (a 3D macrostep is ~30x a cylinder macrostep), 2 warm-up macrosteps."""
+    a = argparse.Namespace(**vars(args))
+    a.steps = max(5, args.steps // 20)
+    a.warmup = 2
+    return a
+
+
 def equal_error(args, h):
-    """MRAB (macrostep 4 hh, O-mesh at hh) and single-rate AB (every grid at
-    hh) for hh in {h, h/2, h/4}, against a single-rate reference at h/16, all
-    from the same initial state and stopped at the same final time T = 4h (m -
-    1 + N) (each bootstrap spans m - 1 of its own macrosteps); error = max |rho
-    - rho_ref| over active points of both grids (the paper's error measure
-    for its convergence tables).  Wall time covers the macrosteps only.  The
-    claim checked: MRAB's error-versus-wall-time curve lies below single-rate
-    AB's (log-log interpolation of the single-rate curve at MRAB's wall
-    times)."""
+    """MRAB (macrostep 4 hh, O-mesh at hh) for hh in {h, h/2, h/4} and
+    single-rate AB (every grid at hh) for hh in {h, h/2, h/4, h/8}, against a
+    single-rate reference at h/32, all from the same initial state and
+    stopped at the same final time T = 4h (m - 1 + N) (each bootstrap spans
+    m - 1 of its own macrosteps); error = max |rho - rho_ref| over active
+    points of both grids (the paper's error measure for its convergence
+    tables).  Wall time covers the macrosteps only.  Single-rate AB cannot
+    step above h (the O-mesh's stable step), so its curve starts at h.
+    Reported: single-rate wall time at each MRAB error (log-log interpolation
+    inside the single-rate points; MRAB's errors lie inside their range) over
+    MRAB's wall time, and single-rate error at each MRAB wall time where that
+    wall time lies inside the single-rate range (None elsewhere: no
+    clamping)."""
     import torch
     from paper_1805_06607_amd.system import System
     N = args.ee_macrosteps
@@ -521,47 +612,90 @@ def equal_error(args, h):
         del s
         return rho, ib, el, t
 
-    ref, ib, el_ref, t_ref = run((1, 1), h / 16, 63 * (m - 1) + 64 * N)
+    # reference: every grid at h/32, T = 4h (m - 1 + N) = (h/32)(m - 1 + n)
+    ref, ib, el_ref, t_ref = run((1, 1), h / 32, 128 * (m - 1 + N) - (m - 1))
 
     def err(rho):
         return max(float(np.max(np.abs(rho[g] - ref[g])[ib[g]])) for g in range(2))
 
-    pts = []
+    mrab, srab = [], []
     for f in (1, 2, 4):
         hh = h / f
         Nh = f * (N + m - 1) - (m - 1)
         rho_m, _, el_m, t_m = run((1, 4), 4 * hh, Nh)
-        rho_s, _, el_s, t_s = run((1, 1), hh, 3 * (m - 1) + 4 * Nh)
-        pts.append({"h": hh, "mrab_macrosteps": Nh, "err_mrab": err(rho_m), "err_srab": err(rho_s),
-                    "wall_s_mrab": el_m, "wall_s_srab": el_s, "T_mrab": t_m, "T_srab": t_s})
-        log(f"equal error h/{f}: err mrab {pts[-1]['err_mrab']:.3e} srab {pts[-1]['err_srab']:.3e}; "
-            f"wall mrab {el_m:.4f}s srab {el_s:.4f}s")
-    # single-rate error at MRAB's wall times (log-log interpolation, clamped to
-    # the measured range) over MRAB's error: > 1 where MRAB is below the curve
-    lw = np.log([p["wall_s_srab"] for p in pts])
-    le = np.log([p["err_srab"] for p in pts])
-    order = np.argsort(lw)
-    below = []
-    for p in pts:
-        x = np.log(p["wall_s_mrab"])
-        e_s = float(np.exp(np.interp(x, lw[order], le[order])))
-        below.append(e_s / p["err_mrab"])
-    first = pts[0]
-    log(f"equal error: T={t_ref:.6g}; single-rate error at MRAB's wall time / MRAB error = "
-        + ", ".join(f"{b:.2f}" for b in below))
+        mrab.append({"h": hh, "macrosteps": Nh, "err": err(rho_m), "wall_s": el_m, "T": t_m})
+        log(f"equal error MRAB h/{f}: err {mrab[-1]['err']:.3e} wall {el_m:.4f}s")
+    for f in (1, 2, 4, 8):
+        hh = h / f
+        ns = 4 * f * (N + m - 1) - (m - 1)
+        rho_s, _, el_s, t_s = run((1, 1), hh, ns)
+        srab.append({"h": hh, "steps": ns, "err": err(rho_s), "wall_s": el_s, "T": t_s})
+        log(f"equal error SRAB h/{f}: err {srab[-1]['err']:.3e} wall {el_s:.4f}s")
+    lw = np.log([p["wall_s"] for p in srab])
+    le = np.log([p["err"] for p in srab])
+    ow, oe = np.argsort(lw), np.argsort(le)
+    wall_ratio, err_ratio = [], []
+    for p in mrab:
+        x = np.log(p["err"])
+        if le[oe][0] <= x <= le[oe][-1]:
+            w_s = float(np.exp(np.interp(x, le[oe], lw[oe])))
+            wall_ratio.append(w_s / p["wall_s"])
+        else:
+            wall_ratio.append(None)
+        x = np.log(p["wall_s"])
+        if lw[ow][0] <= x <= lw[ow][-1]:
+            e_s = float(np.exp(np.interp(x, lw[ow], le[ow])))
+            err_ratio.append(e_s / p["err"])
+        else:
+            err_ratio.append(None)
+    log(f"equal error: T={t_ref:.6g}; single-rate wall time at MRAB's error / MRAB wall time = "
+        + ", ".join("-" if r is None else f"{r:.2f}" for r in wall_ratio))
+    first_m, first_s = mrab[0], srab[0]
     return {"T": t_ref, "mrab_macrosteps": N, "spinup_steps_at_h_over_4": args.ee_spinup,
-            "err_mrab": first["err_mrab"], "err_srab": first["err_srab"],
-            "wall_s_mrab": first["wall_s_mrab"], "wall_s_srab": first["wall_s_srab"],
-            "wall_ratio_srab_over_mrab": first["wall_s_srab"] / first["wall_s_mrab"],
-            "curve": pts, "srab_err_at_mrab_wall_over_mrab_err": below,
-            "mrab_curve_below_srab": bool(all(b > 1.0 for b in below)),
-            "reference": "single-rate AB at h/16", "error": "max |rho - rho_ref| over active points"}
+            "err_mrab": first_m["err"], "err_srab": first_s["err"],
+            "wall_s_mrab": first_m["wall_s"], "wall_s_srab": first_s["wall_s"],
+            "wall_ratio_srab_over_mrab_same_h": first_s["wall_s"] / first_m["wall_s"],
+            "mrab": mrab, "srab": srab,
+            "srab_wall_at_mrab_err_over_mrab_wall": wall_ratio,
+            "srab_err_at_mrab_wall_over_mrab_err": err_ratio,
+            "mrab_faster_at_equal_error": bool(all(r is not None and r > 1.0 for r in wall_ratio)),
+            "reference": "single-rate AB at h/32", "error": "max |rho - rho_ref| over active points"}
+
+
+def _omp():
+    """The OpenMP runtime the oracle's C part runs on (thread count control)."""
+    import ctypes
+    lib = ctypes.CDLL("libgomp.so.1")
+    lib.omp_get_max_threads.restype = ctypes.c_int
+    return lib
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _timed_macrosteps(mr, seconds, min_steps=1):
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        mr.macrostep()
+        k += 1
+        if time.perf_counter() - t0 > seconds and k >= min_steps:
+            break
+    return k, time.perf_counter() - t0
 
 
 def cpu_baseline(args):
     """The oracle (plain C + numpy, OpenMP) on a bounded sample of the same
     workload: MRAB macrosteps from a history of repeated F(y0), timed until
-    ~10 s of work."""
+    ~10 s of work on every core of the host, then for ~5 s on one core."""
     import oracle
     wl = workload((1, 4))
     orc = oracle.OracleSystem(wl)
@@ -572,18 +706,54 @@ def cpu_baseline(args):
     mr.set_history(wl.q0, [[F0[g]] * m for g in range(2)], 0.0)
     n_act = [int(g.iblank.sum()) for g in orc.grids]
     pts = sum(g.rate * n for g, n in zip(wl.grids, n_act))
-    t0 = time.perf_counter()
-    k = 0
-    while True:
-        mr.macrostep()
-        k += 1
-        if time.perf_counter() - t0 > args.cpu_seconds and k >= 2:
-            break
-    el = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    omp = _omp()
+    threads = omp.omp_get_max_threads()
+    k, el = _timed_macrosteps(mr, args.cpu_seconds, 2)
+    omp.omp_set_num_threads(1)
+    k1, el1 = _timed_macrosteps(mr, args.cpu_seconds / 2)
+    omp.omp_set_num_threads(threads)
     return {"value": pts * k / el, "unit": "pt-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{k} MRAB macrosteps of the same cylinder workload (full size) from a "
-                      f"constant history, {el:.1f} s"}
+                      f"constant history, {el:.1f} s",
+            "one_core": {"value": pts * k1 / el1, "cores": 1, "sample": f"{k1} more macrosteps, {el1:.1f} s"},
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def cpu_baseline_3d(args, wl=None):
+    """The oracle on a bounded sample of the 3D three-level workload: one
+    MRAB macrostep (all grids at their rates) from a history of repeated
+    F(y0) on every core, and the right-hand side of the 64^3 inner patch on
+    one core."""
+    import oracle
+    import workloads
+    wl = wl if wl is not None else workloads.tgv3d()
+    t0 = time.perf_counter()
+    orc = oracle.OracleSystem(wl)
+    setup = time.perf_counter() - t0
+    h, H = orc.timestep()
+    mr = orc.integrator(H)
+    F0 = orc.rhs(wl.q0)
+    m = wl.params["hist_len"]
+    mr.set_history(wl.q0, [[F0[g]] * m for g in range(len(wl.grids))], 0.0)
+    n_act = [int(g.iblank.sum()) for g in orc.grids]
+    pts = sum(g.rate * n for g, n in zip(wl.grids, n_act))
+    omp = _omp()
+    threads = omp.omp_get_max_threads()
+    k, el = _timed_macrosteps(mr, 0.0)
+    omp.omp_set_num_threads(1)
+    gi = len(wl.grids) - 1
+    recv = orc.receiver_data(gi, wl.q0)
+    t0 = time.perf_counter()
+    orc.rhs_grid(gi, wl.q0[gi], recv)
+    el1 = time.perf_counter() - t0
+    omp.omp_set_num_threads(threads)
+    return {"value": pts * k / el, "unit": "pt-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{k} MRAB macrostep of the 3D three-level workload (full size) from a constant history, "
+                      f"{el:.1f} s (oracle setup {setup:.0f} s not counted)",
+            "one_core": {"value": n_act[gi] / el1, "cores": 1,
+                         "sample": f"one right-hand side of the {'x'.join(map(str, wl.grids[gi].n))} inner patch "
+                                   f"({n_act[gi]} points), {el1:.1f} s"},
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def main():
@@ -593,6 +763,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-equal-error", action="store_true")
+    ap.add_argument("--no-3d", action="store_true", help="leave out the 3D roofline part of the default run")
     ap.add_argument("--ee-macrosteps", type=int, default=200)
     ap.add_argument("--ee-spinup", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -652,6 +823,7 @@ def main():
             "H": res["mrab"]["H"], "h": res["mrab"]["h"], "tile_shapes": res["mrab"]["tiles"],
         },
         "roofline": res["roofline"],
+        "roofline_cylinder": res["roofline_cylinder"],
         "srab": {
             "value": res["srab"]["pts"] / res["srab"]["time_s"],
             "ms_per_macrostep_equivalent": res["srab"]["time_s"] / res["srab"]["steps"] * 4 * 1e3,
@@ -661,9 +833,15 @@ def main():
     }
     if "equal_error" in res:
         line["equal_error"] = res["equal_error"]
+    if "tgv3d" in res:
+        line["tgv3d"] = {k: v for k, v in res["tgv3d"].items() if k not in ("roofline", "_wl")}
+        line["tgv3d"]["workload"] = TGV3D_WORKLOAD
     if not args.no_cpu:
         log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(args)
+        if "tgv3d" in res:
+            log("cpu baseline (3D)")
+            line["cpu_baseline_3d"] = cpu_baseline_3d(args, res["tgv3d"]["_wl"])
     print(json.dumps(line), flush=True)
 
 

@@ -135,20 +135,20 @@ def test_mrab_parity_100_macrosteps(torch, case, mode):
 @pytest.mark.parametrize("case", ["vortex_box", "cylinder_small"])
 def test_fine_step_single_rate_reference(torch, case):
     """The equal-error protocol's reference run is single-rate AB at a
-    sixteenth of the fast step: the same run on the GPU and in the oracle
-    (every grid at h/16, 128 steps after the bootstrap) agree to 1e-10."""
+    32nd of the fast step: the same run on the GPU and in the oracle
+    (every grid at h/32, 128 steps after the bootstrap) agree to 1e-10."""
     wl = CASES[case]()
     for g in wl.grids:
         g.rate = 1
     from oracle import OracleSystem
     h, _ = OracleSystem(CASES[case]()).timestep()
-    wl.params["dt_fixed"] = h / 16
-    _say("fine-step single-rate reference", case, h / 16)
+    wl.params["dt_fixed"] = h / 32
+    _say("fine-step single-rate reference", case, h / 32)
     orc, mr, sysg = _run_both(wl, 128)
     for g in range(len(wl.grids)):
         act = orc.grids[g].iblank.astype(bool)
         e = rel_l2(_np(sysg.state(g)), mr.y[g], act)
-        _say(case, g, "single-rate at h/16", e)
+        _say(case, g, "single-rate at h/32", e)
         assert np.all(e <= 1e-10), (case, g, e)
 
 
