@@ -164,15 +164,16 @@ hipError_t launch_rhs_tile2d_donor(const GridDev &g, int sbp, const Phys &ph, co
                                    const Combine &cb, int shape, const DonorLink &a, const DonorBlocks &b,
                                    hipStream_t st);
 // 3D Cartesian right-hand side on LDS tiles of shape 0..NUM_TILE3D_SHAPES-1:
-// a gradient pass into grad (dim (dim+1) x npts scratch), then flux
-// divergence + SAT + AB update
+// a gradient pass into grad (the NVISC3 x npts viscous quantities), then
+// flux divergence + SAT + AB update
 struct TileShape3 { int tx, ty, tz; };
-constexpr int NUM_TILE3D_SHAPES = 4;
+constexpr int NUM_TILE3D_SHAPES = 6;
 extern const TileShape3 kTile3dShapes[NUM_TILE3D_SHAPES];
 // slab: tiles are taken in slabs of that many tile rows along y, z planes
-// within a slab (<= 0 or >= the tile rows: the plain x, y, z order)
+// within a slab (<= 0 or >= the tile rows: the plain x, y, z order); the
+// gradient pass takes tiles of grad_shape (-1: shape)
 hipError_t launch_rhs_tile3d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *grad,
-                             double *F, const Combine &cb, int shape, int slab, hipStream_t st);
+                             double *F, const Combine &cb, int shape, int grad_shape, int slab, hipStream_t st);
 // the same right-hand side with the flux pass marching along z (k_rhs_zm3d):
 // gradient pass on tiles of grad_shape (kTile3dShapes), flux pass on columns of
 // shape 1: 16 x 16, 2: 32 x 8, 3: 16 x 8, zc planes per chunk (0: chosen

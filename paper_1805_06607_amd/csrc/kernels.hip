@@ -365,13 +365,18 @@ __global__ void __launch_bounds__(TX * TY * TZ) k_grad_tile3d(GridDev g, Phys ph
     const int64_t p = inside ? (t0[0] + lc[0]) * g.stride[0] + (t0[1] + lc[1]) * g.stride[1] +
                                    (t0[2] + lc[2]) * g.stride[2]
                              : 0;
-    const bool active = inside && (g.cls[p] & 15) != CLS_HOLE;
-    Vec<4> own;
-    if (active) {
-        double qq[5];
-        load_q<3>(q, N, p, qq);
-        own = prim<3>(qq, gm1);
-    } else {
+    // every global load of a point is issued before its class decides what
+    // to keep (a hole's state is read but not used)
+    int row[3] = {CLS_HOLE, CLS_HOLE, CLS_HOLE};
+    double qo[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+    if (inside) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) row[m] = g.cls[m * N + p] & 15;
+        load_q<3>(q, N, p, qo);
+    }
+    const bool active = row[0] != CLS_HOLE;
+    Vec<4> own = prim<3>(qo, gm1);
+    if (!active) {
 #pragma unroll
         for (int a = 0; a < 4; ++a) own.v[a] = 0.0;
     }
@@ -387,26 +392,33 @@ __global__ void __launch_bounds__(TX * TY * TZ) k_grad_tile3d(GridDev g, Phys ph
             const int e = co[0] + ext[0] * (co[1] + ext[1] * co[2]);
             Vec<4> w = own;
             int64_t idx;
-            if (!inside && C::global(g, t0, m, co, idx) && (g.cls[idx] & 15) != CLS_HOLE) {
+            if (!inside && C::global(g, t0, m, co, idx)) {
                 double qq[5];
                 load_q<3>(q, N, idx, qq);
-                w = prim<3>(qq, gm1);
+                if ((g.cls[idx] & 15) != CLS_HOLE) w = prim<3>(qq, gm1);
             }
 #pragma unroll
             for (int a = 0; a < 4; ++a) sW[a][e] = w.v[a];
         }
         const int nh = 2 * R * C::NT / C::T(m);
-        for (int h = tid; h < nh; h += C::NT) {
+        // at most NHI entries per thread, unrolled so that their loads issue together
+        constexpr int NHI = (2 * R * C::NT / (TX < TY ? (TX < TZ ? TX : TZ) : (TY < TZ ? TY : TZ)) + C::NT - 1) / C::NT;
+#pragma unroll
+        for (int it = 0; it < NHI; ++it) {
+            const int h = tid + it * C::NT;
+            if (h >= nh) break;
             int c[3];
             C::halo(m, h, c);
             int64_t idx;
             const bool ok = C::global(g, t0, m, c, idx);
-            Vec<4> w;
-            if (ok && (g.cls[idx] & 15) != CLS_HOLE) {
-                double qq[5];
+            double qq[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+            int ch = CLS_HOLE;
+            if (ok) {
+                ch = g.cls[idx] & 15;
                 load_q<3>(q, N, idx, qq);
-                w = prim<3>(qq, gm1);
-            } else {
+            }
+            Vec<4> w = prim<3>(qq, gm1);
+            if (ch == CLS_HOLE) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a) w.v[a] = 0.0;
             }
@@ -418,7 +430,7 @@ __global__ void __launch_bounds__(TX * TY * TZ) k_grad_tile3d(GridDev g, Phys ph
         if (active) {
             const int base = (lc[0] + (m == 0 ? R : 0)) + ext[0] * ((lc[1] + (m == 1 ? R : 0)) + ext[1] * (lc[2] + (m == 2 ? R : 0)));
             const int step = m == 0 ? 1 : (m == 1 ? ext[0] : ext[0] * ext[1]);
-            dxi[m] = dsbp<SBP, 4>(g.cls[m * N + p] & 15, [&](int o) {
+            dxi[m] = dsbp<SBP, 4>(row[m], [&](int o) {
                 Vec<4> x;
 #pragma unroll
                 for (int a = 0; a < 4; ++a) x.v[a] = sW[a][base + o * step];
@@ -468,11 +480,17 @@ __global__ void __launch_bounds__(TX * TY * TZ) k_rhs_tile3d(GridDev g, Phys ph,
     const int64_t p = inside ? (t0[0] + lc[0]) * g.stride[0] + (t0[1] + lc[1]) * g.stride[1] +
                                    (t0[2] + lc[2]) * g.stride[2]
                              : 0;
-    const bool active = inside && (g.cls[p] & 15) != CLS_HOLE;
+    // every global load of a point is issued before its class decides what
+    // to keep (a hole's state is read but not used)
+    int row[3] = {CLS_HOLE, CLS_HOLE, CLS_HOLE};
     Vec<NV> own[3];
-    if (active) {
+    if (inside) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) row[m] = g.cls[m * N + p] & 15;
         fluxes3(g, ph, q, grad, p, own);
-    } else {
+    }
+    const bool active = row[0] != CLS_HOLE;
+    if (!active) {
 #pragma unroll
         for (int m = 0; m < 3; ++m)
 #pragma unroll
@@ -492,21 +510,31 @@ __global__ void __launch_bounds__(TX * TY * TZ) k_rhs_tile3d(GridDev g, Phys ph,
             // periodic direction m (zero otherwise)
             Vec<NV> f = own[m];
             int64_t idx;
-            if (!inside && C::global(g, t0, m, co, idx) && (g.cls[idx] & 15) != CLS_HOLE)
-                f = fhat_at<3, 1>(g, ph, q, grad, m, idx);
+            if (!inside && C::global(g, t0, m, co, idx)) {
+                Vec<NV> fw = fhat_at<3, 1>(g, ph, q, grad, m, idx);
+                if ((g.cls[idx] & 15) != CLS_HOLE) f = fw;
+            }
 #pragma unroll
             for (int v = 0; v < NV; ++v) sF[v][base] = f.v[v];
         }
         const int nh = 2 * R * C::NT / C::T(m);
-        for (int h = tid; h < nh; h += C::NT) {
+        // at most NHI entries per thread, unrolled so that their loads issue together
+        constexpr int NHI = (2 * R * C::NT / (TX < TY ? (TX < TZ ? TX : TZ) : (TY < TZ ? TY : TZ)) + C::NT - 1) / C::NT;
+#pragma unroll
+        for (int it = 0; it < NHI; ++it) {
+            const int h = tid + it * C::NT;
+            if (h >= nh) break;
             int c[3];
             C::halo(m, h, c);
             int64_t idx;
             const bool ok = C::global(g, t0, m, c, idx);
             Vec<NV> f;
-            if (ok && (g.cls[idx] & 15) != CLS_HOLE) {
+            int ch = CLS_HOLE;
+            if (ok) {
+                ch = g.cls[idx] & 15;
                 f = fhat_at<3, 1>(g, ph, q, grad, m, idx);
-            } else {
+            }
+            if (ch == CLS_HOLE) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) f.v[v] = 0.0;
             }
@@ -517,7 +545,7 @@ __global__ void __launch_bounds__(TX * TY * TZ) k_rhs_tile3d(GridDev g, Phys ph,
         __syncthreads();
         if (active) {
             const int step = m == 0 ? 1 : (m == 1 ? ext[0] : ext[0] * ext[1]);
-            Vec<NV> d = dsbp<SBP, NV>(g.cls[m * N + p] & 15, [&](int o) {
+            Vec<NV> d = dsbp<SBP, NV>(row[m], [&](int o) {
                 Vec<NV> x;
 #pragma unroll
                 for (int v = 0; v < NV; ++v) x.v[v] = sF[v][base + o * step];
@@ -1779,7 +1807,8 @@ hipError_t launch_rhs_tile2d_donor(const GridDev &g, int sbp, const Phys &ph, co
 #define DISPATCH_GRAD(DIM, SBP, CART) \
     hipLaunchKernelGGL((k_grad<DIM, SBP, CART>), dim3(nblk(g.npts, 256)), dim3(256), 0, st, g, ph, q, grad)
 
-const TileShape3 kTile3dShapes[NUM_TILE3D_SHAPES] = {{8, 8, 8}, {16, 8, 4}, {32, 4, 4}, {16, 4, 4}};
+const TileShape3 kTile3dShapes[NUM_TILE3D_SHAPES] = {{8, 8, 8}, {16, 8, 4}, {32, 4, 4}, {16, 4, 4}, {16, 8, 8},
+                                                      {32, 8, 4}};
 
 template <int TX, int TY, int TZ>
 static hipError_t grad3d_shape(const GridDev &g, int sbp, const Phys &ph, const double *q, double *vis, int slab,
@@ -1795,23 +1824,34 @@ static hipError_t grad3d_shape(const GridDev &g, int sbp, const Phys &ph, const 
     return hipGetLastError();
 }
 
+static hipError_t grad3d_launch(const GridDev &g, int sbp, const Phys &ph, const double *q, double *vis, int shape,
+                                int slab, hipStream_t st)
+{
+    switch (shape) {
+    case 0: return grad3d_shape<8, 8, 8>(g, sbp, ph, q, vis, slab, st);
+    case 1: return grad3d_shape<16, 8, 4>(g, sbp, ph, q, vis, slab, st);
+    case 2: return grad3d_shape<32, 4, 4>(g, sbp, ph, q, vis, slab, st);
+    case 3: return grad3d_shape<16, 4, 4>(g, sbp, ph, q, vis, slab, st);
+    case 4: return grad3d_shape<16, 8, 8>(g, sbp, ph, q, vis, slab, st);
+    case 5: return grad3d_shape<32, 8, 4>(g, sbp, ph, q, vis, slab, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+
 template <int TX, int TY, int TZ>
-static hipError_t tile3d_shape(const GridDev &g, int sbp, const Phys &ph, const double *q, double *grad,
+static hipError_t flux3d_shape(const GridDev &g, int sbp, const Phys &ph, const double *q, const double *vis,
                                double *F, const Combine &cb, int slab, hipStream_t st)
 {
     const int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY, ntz = (g.n[2] + TZ - 1) / TZ;
     const int sy = slab > 0 && slab < nty ? slab : nty;
     const dim3 grid((unsigned)(ntx * nty * ntz)), block(TX * TY * TZ);
-    double *gw = grad;
-    if (sbp == 21) {
-        hipLaunchKernelGGL((k_grad_tile3d<21, TX, TY, TZ>), grid, block, 0, st, g, ph, q, gw, ntx, nty, ntz, sy);
-        hipLaunchKernelGGL((k_rhs_tile3d<21, TX, TY, TZ>), grid, block, 0, st, g, ph, q, grad, F, cb, ntx, nty, ntz,
+    if (sbp == 21)
+        hipLaunchKernelGGL((k_rhs_tile3d<21, TX, TY, TZ>), grid, block, 0, st, g, ph, q, vis, F, cb, ntx, nty, ntz,
                            sy);
-    } else {
-        hipLaunchKernelGGL((k_grad_tile3d<42, TX, TY, TZ>), grid, block, 0, st, g, ph, q, gw, ntx, nty, ntz, sy);
-        hipLaunchKernelGGL((k_rhs_tile3d<42, TX, TY, TZ>), grid, block, 0, st, g, ph, q, grad, F, cb, ntx, nty, ntz,
+    else
+        hipLaunchKernelGGL((k_rhs_tile3d<42, TX, TY, TZ>), grid, block, 0, st, g, ph, q, vis, F, cb, ntx, nty, ntz,
                            sy);
-    }
     return hipGetLastError();
 }
 
@@ -1843,14 +1883,7 @@ hipError_t launch_rhs_zm3d(const GridDev &g, int sbp, const Phys &ph, const doub
                            int nsat, hipStream_t st)
 {
     if (g.dim != 3 || !g.cartesian || (sbp != 21 && sbp != 42)) return hipErrorInvalidValue;
-    hipError_t e;
-    switch (grad_shape) {
-    case 0: e = grad3d_shape<8, 8, 8>(g, sbp, ph, q, vis, slab, st); break;
-    case 1: e = grad3d_shape<16, 8, 4>(g, sbp, ph, q, vis, slab, st); break;
-    case 2: e = grad3d_shape<32, 4, 4>(g, sbp, ph, q, vis, slab, st); break;
-    case 3: e = grad3d_shape<16, 4, 4>(g, sbp, ph, q, vis, slab, st); break;
-    default: return hipErrorInvalidValue;
-    }
+    hipError_t e = grad3d_launch(g, sbp, ph, q, vis, grad_shape, slab, st);
     if (e != hipSuccess) return e;
     switch (shape) {
     case 1: return zm3d_shape<16, 16>(g, sbp, ph, q, vis, F, cb, zc, satpts, nsat, st);
@@ -1861,14 +1894,18 @@ hipError_t launch_rhs_zm3d(const GridDev &g, int sbp, const Phys &ph, const doub
 }
 
 hipError_t launch_rhs_tile3d(const GridDev &g, int sbp, const Phys &ph, const double *q, double *grad,
-                             double *F, const Combine &cb, int shape, int slab, hipStream_t st)
+                             double *F, const Combine &cb, int shape, int grad_shape, int slab, hipStream_t st)
 {
     if (g.dim != 3 || !g.cartesian || (sbp != 21 && sbp != 42)) return hipErrorInvalidValue;
+    hipError_t e = grad3d_launch(g, sbp, ph, q, grad, grad_shape < 0 ? shape : grad_shape, slab, st);
+    if (e != hipSuccess) return e;
     switch (shape) {
-    case 0: return tile3d_shape<8, 8, 8>(g, sbp, ph, q, grad, F, cb, slab, st);
-    case 1: return tile3d_shape<16, 8, 4>(g, sbp, ph, q, grad, F, cb, slab, st);
-    case 2: return tile3d_shape<32, 4, 4>(g, sbp, ph, q, grad, F, cb, slab, st);
-    case 3: return tile3d_shape<16, 4, 4>(g, sbp, ph, q, grad, F, cb, slab, st);
+    case 0: return flux3d_shape<8, 8, 8>(g, sbp, ph, q, grad, F, cb, slab, st);
+    case 1: return flux3d_shape<16, 8, 4>(g, sbp, ph, q, grad, F, cb, slab, st);
+    case 2: return flux3d_shape<32, 4, 4>(g, sbp, ph, q, grad, F, cb, slab, st);
+    case 3: return flux3d_shape<16, 4, 4>(g, sbp, ph, q, grad, F, cb, slab, st);
+    case 4: return flux3d_shape<16, 8, 8>(g, sbp, ph, q, grad, F, cb, slab, st);
+    case 5: return flux3d_shape<32, 8, 4>(g, sbp, ph, q, grad, F, cb, slab, st);
     default: return hipErrorInvalidValue;
     }
 }

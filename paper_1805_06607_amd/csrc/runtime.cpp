@@ -150,6 +150,7 @@ struct mr_ctx {
     bool donor_blocks = true; // one-launch donor data for links whose chunks fit one workgroup
     bool ride_donors = true;  // one stream: mid-step donor data in the next same-time 2D evaluation's launch
     int tile3d = 1;           // 3D passes: LDS tile shape (mrk::kTile3dShapes), -1 the per-point kernels
+    int gtile3d = 4;          // 3D gradient pass: its own tile shape (-1: tile3d)
     int slab3d = 3;           // 3D passes: tile rows per slab of the tile order (0: plain x, y, z order)
     int flux3d = 0;           // 3D flux pass: 0 on tiles, 1..3 marching along z (columns 16x16, 32x8, 16x8)
     int zchunk3d = 0;         // 3D z-marching flux pass: planes per chunk (0: from the grid size)
@@ -852,7 +853,8 @@ int grid_rhs(mr_ctx *c, int gi, const double *q, double *F, const mrk::Combine &
         HIPCHK(c, mrk::launch_rhs_zm3d(dev, c->P.sbp, c->ph, q, g.grad, F, cb, c->tile3d, c->slab3d, c->flux3d,
                                        c->zchunk3d, g.satpts_d, (int)g.satpts.size(), st));
     } else if (g.dim == 3 && c->tile3d >= 0) {
-        HIPCHK(c, mrk::launch_rhs_tile3d(dev, c->P.sbp, c->ph, q, g.grad, F, cb, c->tile3d, c->slab3d, st));
+        HIPCHK(c, mrk::launch_rhs_tile3d(dev, c->P.sbp, c->ph, q, g.grad, F, cb, c->tile3d, c->gtile3d, c->slab3d,
+                                         st));
     } else {
         HIPCHK(c, mrk::launch_grad(dev, c->P.sbp, c->ph, q, g.grad, st));
         HIPCHK(c, mrk::launch_rhs(dev, c->grids_d + gi, c->P.sbp, c->ph, q, g.grad, F, cb, st));
@@ -2803,6 +2805,10 @@ int mr_set_option(mr_ctx *c, const char *name, int64_t value)
     } else if (!strcmp(name, "tile3d_slab")) {
         if (value < 0 || value > 1024) return fail(c, MR_ERR_ARG, "tile3d_slab must be 0 .. 1024");
         c->slab3d = (int)value;
+    } else if (!strcmp(name, "grad_tile3d")) {
+        if (value < -1 || value >= mrk::NUM_TILE3D_SHAPES)
+            return fail(c, MR_ERR_ARG, "grad_tile3d must be -1 .. %d", mrk::NUM_TILE3D_SHAPES - 1);
+        c->gtile3d = (int)value;
     } else if (!strcmp(name, "rhs_tile3d")) {
         if (value < -1 || value >= mrk::NUM_TILE3D_SHAPES)
             return fail(c, MR_ERR_ARG, "rhs_tile3d must be -1 .. %d", mrk::NUM_TILE3D_SHAPES - 1);

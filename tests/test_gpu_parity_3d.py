@@ -30,12 +30,14 @@ def small():
     return workloads.tgv3d(nbg=48, npatch=24, ninner=16)
 
 
-@pytest.mark.parametrize("tile3d,flux3d,zchunk", [
-    (-1, 0, 0), (0, 0, 0), (1, 0, 0), (2, 0, 0), (3, 0, 0),
-    (1, 1, 0), (1, 2, 0), (1, 3, 0), (0, 1, 5), (1, 1, 7), (2, 2, 13), (3, 3, 48)])
-def test_rhs_parity_3d(torch, tile3d, flux3d, zchunk):
+@pytest.mark.parametrize("tile3d,gtile3d,flux3d,zchunk", [
+    (-1, -1, 0, 0), (0, -1, 0, 0), (1, -1, 0, 0), (2, -1, 0, 0), (3, -1, 0, 0), (4, -1, 0, 0), (5, -1, 0, 0),
+    (1, 4, 0, 0), (0, 5, 0, 0), (5, 2, 0, 0),
+    (1, 1, 1, 0), (1, 1, 2, 0), (1, 1, 3, 0), (0, 0, 1, 5), (1, 4, 1, 7), (2, 2, 2, 13), (3, 3, 3, 48)])
+def test_rhs_parity_3d(torch, tile3d, gtile3d, flux3d, zchunk):
     """Point-wise flux kernel (-1), every LDS tile shape of the gradient and
-    flux passes, and the z-marching flux pass on every column shape with
+    flux passes (the same one for both, or different ones), and the
+    z-marching flux pass on every column shape with
     chunks of planes that leave a shorter last chunk (5, 7, 13) or hold a
     whole grid (48); the 32-wide and 4-deep tiles leave partial tiles on
     these grids."""
@@ -47,13 +49,14 @@ def test_rhs_parity_3d(torch, tile3d, flux3d, zchunk):
     want = orc.rhs(states)
     sysg = System(wl)
     sysg.set_option("rhs_tile3d", tile3d)
+    sysg.set_option("grad_tile3d", gtile3d)
     sysg.set_option("flux3d", flux3d)
     sysg.set_option("zchunk3d", zchunk)
     got = sysg.rhs(states)
     for g in range(len(wl.grids)):
         act = orc.grids[g].iblank.astype(bool)
         e = rel_l2(_np(got[g]), want[g], act)
-        _say("3d rhs", tile3d, flux3d, zchunk, g, e)
+        _say("3d rhs", tile3d, gtile3d, flux3d, zchunk, g, e)
         assert np.all(e <= 1e-12), (g, e)
         assert np.all(_np(got[g])[:, ~act] == 0.0)
 
