@@ -345,6 +345,17 @@ int mr_batch_macrostep(mr_batch *batch, int nsteps);
  * batch fills the GPU with many grids at once, so large tiles (shape 0, 32 x
  * 16) usually beat the small multi-thread tiles that suit one small grid. */
 int mr_batch_set_tile_shape(mr_batch *batch, int shape);
+/* Autotuner of the batch's tile shape: times `reps` passes of one fused
+ * right-hand side of every grid of every system (from the current states
+ * into the systems' scratch buffers: states, histories and times are not
+ * changed) for each candidate -- every grid's own shape (-1), then each shape
+ * 0 .. MR_NUM_TILE_SHAPES-1 for all -- with HIP events around back-to-back
+ * launches, keeps the fastest as the batch's shape and returns it in *shape.
+ * ms (may be NULL): MR_NUM_TILE_SHAPES + 1 host doubles, the time of one pass
+ * per candidate in the same order.  Synchronises the stream.
+ * Errors: MR_ERR_ARG (reps outside 1..1000), MR_ERR_STATE (not bound, a
+ * system not started), MR_ERR_HIP. */
+int mr_batch_autotune(mr_batch *batch, int reps, int *shape, double *ms);
 const char *mr_batch_last_error(const mr_batch *batch);
 void mr_batch_destroy(mr_batch *batch);
 

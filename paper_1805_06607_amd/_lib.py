@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmrab.so")
 
 MR_OK = 0
+NUM_TILE_SHAPES = 8          # MR_NUM_TILE_SHAPES of mrab.h
 STATUS = {0: "MR_OK", -1: "MR_ERR_ARG", -2: "MR_ERR_STATE", -3: "MR_ERR_SETUP", -4: "MR_ERR_HIP",
           -5: "MR_ERR_NONFINITE", -6: "MR_ERR_UNSUPPORTED"}
 
@@ -74,6 +75,7 @@ SIGNATURES = {
     "mr_batch_bind_workspace": [c_void_p, c_void_p, c_size_t],
     "mr_batch_macrostep": [c_void_p, c_int],
     "mr_batch_set_tile_shape": [c_void_p, c_int],
+    "mr_batch_autotune": [c_void_p, c_int, POINTER(c_int), POINTER(c_double)],
     "mr_batch_last_error": [c_void_p],
     "mr_batch_destroy": [c_void_p],
     "mr_save_bytes": [c_void_p, POINTER(c_size_t)],

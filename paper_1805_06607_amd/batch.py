@@ -39,6 +39,15 @@ class Batch:
         grid's own, which keeps every system bitwise equal to its own runs)."""
         self._check(self.lib.mr_batch_set_tile_shape(self.b, shape), "mr_batch_set_tile_shape")
 
+    def autotune(self, reps: int = 10):
+        """Time every tile shape (and each grid's own) on one right-hand side
+        of every grid, keep the fastest; returns (shape, {shape: ms})."""
+        from ctypes import c_double, c_int
+        shape = c_int()
+        ms = (c_double * (_lib.NUM_TILE_SHAPES + 1))()
+        self._check(self.lib.mr_batch_autotune(self.b, reps, byref(shape), ms), "mr_batch_autotune")
+        return shape.value, {s - 1: ms[s] for s in range(_lib.NUM_TILE_SHAPES + 1)}
+
     def macrostep(self, n: int = 1):
         self._check(self.lib.mr_batch_macrostep(self.b, n), "mr_batch_macrostep")
 

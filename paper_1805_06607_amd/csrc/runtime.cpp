@@ -3009,6 +3009,103 @@ int mr_batch_macrostep(mr_batch *b, int nsteps)
     return MR_OK;
 }
 
+int mr_batch_autotune(mr_batch *b, int reps, int *shape, double *ms)
+{
+    if (!b || reps < 1 || reps > 1000) return MR_ERR_ARG;
+    if (!b->bound) return bfail(b, MR_ERR_STATE, "mr_batch_autotune before mr_batch_bind_workspace");
+    const int n = (int)b->ctx.size();
+    for (int s = 0; s < n; ++s)
+        if (!b->ctx[s]->started || static_lost(b->ctx[s]))
+            return bfail(b, MR_ERR_STATE, "a system is not started");
+    // one fused right-hand side of every grid of every system, from its
+    // current state into its bootstrap scratch buffers (the states, histories
+    // and the batch's plan period are not touched), per candidate: every
+    // grid's own shape (-1), then each shape for all
+    std::vector<mrk::TileJob> base;
+    for (int s = 0; s < n; ++s) {
+        mr_ctx *c = b->ctx[s];
+        for (int gi = 0; gi < (int)c->G.size(); ++gi) {
+            GridHost &g = c->G[gi];
+            mrk::TileJob J{};
+            J.g = g.dev;
+            J.g.recv = recv_slice(c, g, 1);
+            J.q = g.y[g.cur];
+            J.F = g.rk[0];
+            J.cb.m = c->P.hist_len;
+            for (int j = 0; j < J.cb.m - 1; ++j) {
+                J.cb.c[j] = 0.0;
+                J.cb.hist[j] = slot(c, g, j);
+            }
+            J.cb.c[J.cb.m - 1] = 0.0;
+            J.cb.y_next = g.rk[1];
+            J.tile0 = shape_of(g);
+            base.push_back(J);
+        }
+    }
+    if (base.size() > b->tj_cap) return bfail(b, MR_ERR_STATE, "timing jobs exceed the workspace");
+    hipEvent_t e0, e1;
+    BHIPCHK(b, hipEventCreate(&e0));
+    BHIPCHK(b, hipEventCreate(&e1));
+    b->built = false;   // the timing jobs take the plan's job table
+    double best = INFINITY;
+    int pick = -1;
+    int rc = MR_OK;
+    for (int cand = -1; cand < mrk::NUM_TILE_SHAPES && rc == MR_OK; ++cand) {
+        std::vector<mrk::TileJob> tiles = base, tj;
+        for (auto &J : tiles) {
+            const int sh = cand >= 0 ? cand : J.tile0;
+            const mrk::TileShape &t = mrk::kTileShapes[sh];
+            J.tile0 = sh;
+            J.ntx = (J.g.n[0] + t.tx - 1) / t.tx;
+            J.nty = (J.g.n[1] + t.ty - 1) / t.ty;
+        }
+        std::vector<mr_batch::Launch> out;
+        auto tkey = [&](const mrk::TileJob &j) { return std::array<int, 5>{2, 0, j.g.cartesian, j.tile0, 0}; };
+        auto tcount = [&](mrk::TileJob &j, int &off, mr_batch::Launch &L) {
+            j.tile0 = off;
+            off += j.ntx * j.nty;
+            L.maxnj = 1;
+        };
+        batch_group(tiles, tkey, tcount, 1, tj, out);
+        hipError_t e = hipMemcpyAsync(b->tj_d, tj.data(), tj.size() * sizeof(mrk::TileJob), hipMemcpyHostToDevice,
+                                      b->st);
+        auto all = [&]() {
+            hipError_t x = hipSuccess;
+            for (const auto &L : out)
+                if (x == hipSuccess)
+                    x = mrk::launch_rhs_tiles(b->tj_d + L.first, L.njobs, L.nblk, b->ctx[0]->P.sbp, L.cart, L.shape,
+                                              b->ctx[0]->ph, b->st);
+            return x;
+        };
+        // a warm-up pass, then a wait on the device long enough for the host
+        // to queue every timed pass behind it
+        if (e == hipSuccess) e = all();
+        if (e == hipSuccess) e = mrk::launch_wait_us(100.0 * reps + 200.0, b->st);
+        if (e == hipSuccess) e = hipEventRecord(e0, b->st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = all();
+        if (e == hipSuccess) e = hipEventRecord(e1, b->st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess) {
+            rc = bfail(b, MR_ERR_HIP, hipGetErrorString(e));
+            break;
+        }
+        const double per = (double)t / reps;
+        if (ms) ms[cand + 1] = per;
+        if (per < best) {
+            best = per;
+            pick = cand;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    b->shape = pick;
+    if (shape) *shape = pick;
+    return MR_OK;
+}
+
 int mr_batch_set_tile_shape(mr_batch *b, int shape)
 {
     if (!b || shape < -1 || shape >= mrk::NUM_TILE_SHAPES) return MR_ERR_ARG;

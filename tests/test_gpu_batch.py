@@ -136,3 +136,37 @@ def test_batch_systems_match_oracle_after_100_macrosteps(torch):
             _say("batch vs oracle", i, "rate", wl.grids[1].rate, "grid", g, e)
             assert np.all(e <= 1e-10), (i, g, e)
     b.close()
+
+
+def test_batch_autotune(torch):
+    """The batch autotuner times every candidate, leaves every system's
+    states, histories and time unchanged, and keeps the fastest shape, with
+    which the batch still equals each system run alone with that shape."""
+    from paper_1805_06607_amd.batch import Batch
+    wls = workloads.batch_vortex(5, seed=11, smin=40, smax=96)
+    grouped = _systems(wls)
+    before = [_snap(s) for s in grouped]
+    times = [s.time() for s in grouped]
+    b = Batch(grouped)
+    shape, ms = b.autotune(reps=3)
+    torch.cuda.synchronize()
+    _say("batch autotune pick", shape, {k: round(v, 4) for k, v in ms.items()})
+    assert -1 <= shape < 8 and len(ms) == 9 and all(v > 0 for v in ms.values())
+    assert ms[shape] == min(ms.values())
+    for s, snap, t in zip(grouped, before, times):
+        assert s.time() == t
+        for x, y in zip(_snap(s), snap):
+            assert torch.equal(x, y)
+    solo = _systems(workloads.batch_vortex(5, seed=11, smin=40, smax=96))
+    if shape >= 0:
+        for s in solo:
+            for g in range(s.ngrids):
+                s.set_tile_shape(g, shape)
+    b.macrostep(8)
+    for s in solo:
+        s.macrostep(8)
+    torch.cuda.synchronize()
+    for a, c in zip(solo, grouped):
+        for x, y in zip(_snap(a), _snap(c)):
+            assert torch.equal(x, y)
+    b.close()

@@ -1,6 +1,7 @@
 """GPU parity on the 3D three-level case (periodic background, two patches at
 half spacing, an inner patch at quarter spacing; rates 1, 2, 2, 4; SBP 4-2,
 cubic donors, AB3) against the oracle."""
+import os
 import sys
 
 import numpy as np
@@ -182,10 +183,15 @@ def _near_boundary(ib, n, reach=3):
     return np.flatnonzero((near & act).ravel())
 
 
+SAMPLES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "tgv3d_mrab100_samples.npz")
+
+
 @pytest.fixture(scope="module")
 def full3d(torch):
     from paper_1805_06607_amd.system import System
     wl = workloads.tgv3d()
+    # the macrostep of the stored oracle run (the oracle's own estimate)
+    wl.params["dt_fixed"] = float(np.load(SAMPLES)["H"])
     _say("full-size 3D setup", [g.n for g in wl.grids])
     return wl, System(wl)
 
@@ -261,3 +267,27 @@ def test_full_size_multi_stream_bitwise_3d(torch, full3d):
     for g, (a, b) in enumerate(zip(*outs)):
         assert torch.isfinite(a).all(), g
         assert torch.equal(a, b), g
+
+
+def test_full_size_mrab_100_macrosteps_3d(torch, full3d):
+    """Full-size 3D case with the bench's launch plan: the RK3 bootstrap and
+    100 MRAB macrosteps from the Taylor-Green initial state, against the
+    oracle's run of the same problem at the same macrostep, stored at 3000
+    active points per grid (half of them within three points of a hole, an
+    interface face or a grid edge) by tests/golden/make_tgv3d_samples.py,
+    which calls only the oracle: relative L2 per variable <= 1e-10."""
+    ref = np.load(SAMPLES)
+    wl, sysg = full3d
+    sysg.set_states(wl.q0)
+    h, H = sysg.timestep()
+    assert H == float(ref["H"])
+    sysg.start(0.0)
+    sysg.macrostep(int(ref["nmacro"]))
+    t, k = sysg.time()
+    assert k == int(ref["nmacro"]) and abs(t - float(ref["t"])) <= 1e-12 * t
+    for g in range(len(wl.grids)):
+        pts = ref[f"pts{g}"]
+        got = _np(sysg.state(g))[:, pts]
+        e = rel_l2(got, ref[f"q{g}"])
+        _say("full 3d mrab 100 vs oracle samples", g, pts.size, e)
+        assert np.all(e <= 1e-10), (g, e)
