@@ -176,18 +176,16 @@ def run_batch(args):
     pts = sum(g.rate * int(ib.sum()) for s in systems for g, ib in zip(s.wl.grids, s.iblanks))
     npts = sum(g.npts for wl in wls for g in wl.grids)
     b = Batch(systems)
-    shapes = {}
-    for shape in (-1, 0):          # each grid's own tile shape; 32 x 16 tiles everywhere
-        b.set_tile_shape(shape)
-        b.macrostep(args.warmup)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        b.macrostep(args.steps)
-        torch.cuda.synchronize()
-        shapes[shape] = time.perf_counter() - t0
-        log(f"batch tile shape {shape}: {shapes[shape] / args.steps * 1e3:.3f} ms per macrostep")
-    best = min(shapes, key=shapes.get)
-    el_b = shapes[best]
+    best, tune_ms = b.autotune(reps=10)
+    log(f"batch autotuner: shape {best}; ms per pass by shape (-1: each grid's own): "
+        + ", ".join(f"{k}: {v:.3f}" for k, v in tune_ms.items()))
+    b.macrostep(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.macrostep(args.steps)
+    torch.cuda.synchronize()
+    el_b = time.perf_counter() - t0
+    log(f"batch: {args.steps} macrosteps {el_b * 1e3:.1f} ms")
     for s in systems:
         s.macrostep(args.warmup)
     torch.cuda.synchronize()
@@ -205,7 +203,7 @@ def run_batch(args):
             "config": {"workload": "64 vortex systems, background U{64..512}^2 + patch U{S/4..S/2}^2, rates "
                                    "{1,2,4}, SBP 2-1, bilinear, AB3, seed 3", "points": npts,
                        "point_updates_per_macrostep": pts},
-            "tile_shape": best, "ms_per_step_by_tile_shape": {str(s): t / args.steps * 1e3 for s, t in shapes.items()},
+            "tile_shape": best, "autotune_ms_per_rhs_pass_by_tile_shape": {str(k): v for k, v in tune_ms.items()},
             "one_system_at_a_time": {"value": pts * ks / el_s, "ms_per_step": el_s / ks * 1e3},
             "batch_speedup": (el_s / ks) / (el_b / args.steps),
             "algorithmic_GB_per_s": pts * bpp * args.steps / el_b / 1e9,
