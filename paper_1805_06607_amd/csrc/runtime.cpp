@@ -2681,6 +2681,8 @@ int mr_kernel_time(mr_ctx *c, double *total_ms, int *count) { return mr_kernel_t
 namespace {
 // ---- checkpoints: 256-byte header, then per grid the state and the history
 // values oldest first
+// checkpoint header (256 bytes): the problem it belongs to (scheme, and per
+// grid its sizes and rate) and the integrator's time, macrostep count and H
 struct SaveHeader {
     char magic[8];
     uint32_t version, ngrids;
@@ -2688,8 +2690,20 @@ struct SaveHeader {
     double t, H;
     int64_t nmacro, npts_total;
     uint64_t bytes;
-    char pad[256 - 64];
+    int32_t sbp, order;
+    int32_t grid[mrk::MAXG][4];   // n[0..2], rate
+    char pad[256 - 64 - 8 - 16 * mrk::MAXG];
 };
+
+void save_problem(const mr_ctx *c, SaveHeader &h)
+{
+    h.sbp = c->P.sbp;
+    h.order = c->P.order;
+    for (size_t g = 0; g < c->G.size(); ++g) {
+        for (int k = 0; k < 3; ++k) h.grid[g][k] = c->G[g].n[k];
+        h.grid[g][3] = c->G[g].rate;
+    }
+}
 static_assert(sizeof(SaveHeader) == 256, "checkpoint header size");
 
 size_t save_bytes(const mr_ctx *c)
@@ -2728,8 +2742,9 @@ int mr_save(mr_ctx *c, void *dev, size_t bytes)
     if ((uintptr_t)dev % 8) return fail(c, MR_ERR_ARG, "checkpoint buffer not 8-byte aligned");
     SaveHeader h{};
     std::memcpy(h.magic, "MRABSAVE", 8);
-    h.version = 1;
+    h.version = 2;
     h.ngrids = (uint32_t)c->G.size();
+    save_problem(c, h);
     h.hist_len = c->P.hist_len;
     h.dim = c->P.dim;
     h.t = c->t;
@@ -2763,10 +2778,13 @@ int mr_load(mr_ctx *c, const void *dev, size_t bytes)
     SaveHeader h{};
     HIPCHK(c, hipStreamSynchronize(c->st));
     HIPCHK(c, hipMemcpy(&h, dev, sizeof h, hipMemcpyDeviceToHost));
-    if (std::memcmp(h.magic, "MRABSAVE", 8) || h.version != 1) return fail(c, MR_ERR_SETUP, "not a checkpoint");
+    if (std::memcmp(h.magic, "MRABSAVE", 8) || h.version != 2) return fail(c, MR_ERR_SETUP, "not a checkpoint");
+    SaveHeader mine{};
+    save_problem(c, mine);
     if (h.ngrids != c->G.size() || h.hist_len != c->P.hist_len || h.dim != c->P.dim ||
-        h.npts_total != npts_total(c) || h.bytes != save_bytes(c))
-        return fail(c, MR_ERR_SETUP, "checkpoint of a different problem");
+        h.npts_total != npts_total(c) || h.bytes != save_bytes(c) || h.sbp != mine.sbp || h.order != mine.order ||
+        std::memcmp(h.grid, mine.grid, sizeof h.grid))
+        return fail(c, MR_ERR_SETUP, "checkpoint of a different problem (scheme, grid sizes or rates differ)");
     if (bytes < h.bytes) return fail(c, MR_ERR_ARG, "checkpoint buffer shorter than its header states");
     int rc = set_macrostep(c, h.H);
     if (rc) return rc;

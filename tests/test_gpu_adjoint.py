@@ -275,3 +275,69 @@ def test_adj_terminal_adjoint_without_objective(torch, nmacro):
         fd = richardson(f, 1e-4)
         _say("terminal", nmacro, k, got, fd)
         assert abs(got - fd) <= 1e-7 * abs(fd)
+
+
+TINY = {
+    "vortex_box_21": lambda: workloads.vortex_box(nbg=20, npatch=14, Re=100.0),
+    "cylinder_42": lambda: workloads.cylinder(nbg=40, ntheta=32, nr=12, half=6.0),
+    "wall_channel_42": lambda: workloads.wall_channel(12),
+}
+
+
+@pytest.mark.parametrize("case", list(TINY))
+def test_adj_rhs_whole_field_vs_dense_jacobian(torch, case):
+    """J^T w of the GPU adjoint against the transpose of the oracle's dense
+    Jacobian (central differences with one Richardson step, one column per
+    active state entry), entry
+    by entry over every grid: interfaces with bilinear and cubic donors,
+    periodic seams, far-field faces, isothermal walls on the O-mesh and on
+    Cartesian faces, curvilinear metrics."""
+    from oracle import OracleSystem
+    from paper_1805_06607_amd.adjoint import Adjoint
+    from paper_1805_06607_amd.system import System
+    wl = TINY[case]()
+    states = _base(wl, 7)
+    orc = OracleSystem(wl)
+    sysg = System(wl)
+    adj = Adjoint(sysg, nsnap=1)
+    rng = np.random.default_rng(17)
+    w = [rng.standard_normal(s.shape) for s in states]
+    got = [_np(a) for a in adj.rhs_vjp(states, w)]
+    nv = wl.dim + 2
+    want = [np.zeros_like(s) for s in states]
+    # step scale per variable: the momentum components share the largest
+    # momentum magnitude (a nearly zero component would otherwise get a step
+    # so small that rounding swamps the difference)
+    scale = []
+    for st in states:
+        sc = np.max(np.abs(st), axis=1)
+        sc[1:nv - 1] = np.max(sc[1:nv - 1])
+        scale.append(sc)
+    ncol = 0
+    for g, gr in enumerate(orc.grids):
+        act = np.flatnonzero(gr.iblank)
+        for v in range(nv):
+            for p in act:
+                h = 1e-4 * max(abs(states[g][v, p]), scale[g][v])
+
+                def central(hh):
+                    plus = [s.copy() for s in states]
+                    minus = [s.copy() for s in states]
+                    plus[g][v, p] += hh
+                    minus[g][v, p] -= hh
+                    fp, fm = orc.rhs(plus), orc.rhs(minus)
+                    return sum(float(np.sum(w[k] * (fp[k] - fm[k]))) for k in range(len(states))) / (2 * hh)
+
+                # one Richardson step: error O(h^4) plus rounding
+                want[g][v, p] = (4.0 * central(0.5 * h) - central(h)) / 3.0
+                ncol += 1
+    _say(case, "dense Jacobian columns", ncol)
+    for g, gr in enumerate(orc.grids):
+        act = gr.iblank.astype(bool)
+        assert np.all(got[g][:, ~act] == 0.0), g
+        for v in range(nv):
+            a, b = got[g][v, act], want[g][v, act]
+            tol = 1e-7 * np.maximum(np.abs(b), 1e-3 * np.max(np.abs(b)))
+            err = np.abs(a - b)
+            _say(case, "grid", g, "var", v, "max |err| / tol", float(np.max(err / tol)))
+            assert np.all(err <= tol), (case, g, v, float(np.max(err / tol)))

@@ -59,3 +59,27 @@ def test_load_rejects_other_problem(torch):
         b.load(ck)
     with pytest.raises(_lib.MrabError):
         a.load(ck[:100])
+
+
+def test_load_rejects_same_size_other_problem(torch):
+    """Checkpoints of problems with the same grids and point counts but
+    another rate or another scheme are refused (the header records the
+    scheme and every grid's sizes and rate)."""
+    from paper_1805_06607_amd import _lib
+    from paper_1805_06607_amd.system import System
+    a = System(workloads.vortex_box(rate_patch=2))
+    a.timestep()
+    a.start(0.0)
+    ck = a.save()
+    # same grids, other patch rate
+    with pytest.raises(_lib.MrabError, match="different problem"):
+        System(workloads.vortex_box(rate_patch=4)).load(ck)
+    # same grids, rates and history length, other order (AB2 on 3 values)
+    w = workloads.vortex_box(rate_patch=2)
+    w.params["order"] = 2
+    with pytest.raises(_lib.MrabError, match="different problem"):
+        System(w).load(ck)
+    # the same problem loads
+    b = System(workloads.vortex_box(rate_patch=2))
+    b.load(ck)
+    assert b.time() == a.time()
