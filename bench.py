@@ -82,9 +82,9 @@ def tgv3d_measure(args):
     # launch durations from a single-stream pass (on the per-grid streams the
     # grids' launches overlap and each event pair would also time the others)
     s.set_option("multi_stream", 0)
-    roof = timed_pass(s, wl, n_act, args.steps, "gradient pass + flux divergence, SAT and fused AB update on "
-                                                "LDS tiles (k_grad_tile3d + k_rhs_tile3d), all grids' launches "
-                                                "of a macrostep")
+    roof = timed_pass(s, wl, n_act, args.steps, "gradient pass (viscous stress and heat terms) + flux divergence, "
+                                                "SAT and fused AB update on LDS tiles (k_grad_tile3d 16x8x8 + "
+                                                "k_rhs_tile3d 16x8x4), all grids' launches of a macrostep")
     roof["workload"] = TGV3D_WORKLOAD
     s.close()
     return {"value": pts * args.steps / el, "unit": "pt-updates/s", "ms_per_step": el / args.steps * 1e3,
@@ -321,7 +321,8 @@ def run_adjoint(args):
     print(json.dumps(line), flush=True)
 
 
-TILE3D = (16, 8, 4)   # the 3D passes' default LDS tile (option rhs_tile3d = 1)
+TILE3D = (16, 8, 4)   # the 3D flux pass's default LDS tile (option rhs_tile3d = 1)
+GRAD3D = (16, 8, 8)   # the 3D gradient pass's default LDS tile (option grad_tile3d = 4)
 
 
 def kernel_names(sysg, wl):
@@ -332,13 +333,14 @@ def kernel_names(sysg, wl):
     names = []
     sbp = int(wl.params["sbp"])
     if wl.dim == 3:
-        tile = "{}, {}, {}".format(*TILE3D)
+        tile, gtile = "{}, {}, {}".format(*TILE3D), "{}, {}, {}".format(*GRAD3D)
         for gr in wl.grids:
-            threads = 1
-            for n, t in zip(gr.n, TILE3D):
+            threads, gthreads = 1, 1
+            for n, t, u in zip(gr.n, TILE3D, GRAD3D):
                 threads *= -(-n // t) * t
+                gthreads *= -(-n // u) * u
             names.append((f"tile3d_pair grid={threads}",
-                          [f"k_grad_tile3d<{sbp}, {tile}> grid={threads}",
+                          [f"k_grad_tile3d<{sbp}, {gtile}> grid={gthreads}",
                            f"k_rhs_tile3d<{sbp}, {tile}> grid={threads}"]))
         return names
     for g, gr in enumerate(wl.grids):
