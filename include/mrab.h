@@ -230,10 +230,14 @@ int mr_save_bytes(const mr_ctx *ctx, size_t *bytes);
 int mr_save(mr_ctx *ctx, void *dev_buf, size_t bytes);
 int mr_load(mr_ctx *ctx, const void *dev_buf, size_t bytes);
 
-/* AB coefficients (host, pure): alpha_j, j = 0..hist_len-1 oldest first, for
- * history nodes -(m-1)..0 in units of the step and target offset tau in (0,1]
- * (eq. vandermonde; minimum norm when hist_len > order, eq. ext_ab). */
-int mr_ab_coeffs(int order, int hist_len, double tau, double *out);
+/* AB coefficients (host, pure): spacing * alpha_j, j = 0..hist_len-1 oldest
+ * first, for history nodes -(m-1)..0 in units of the step and target offset
+ * tau in (0,1] (eq. vandermonde; minimum norm when hist_len > order, eq.
+ * ext_ab); alpha_j is rounded to double once, then multiplied by spacing (the
+ * level's step), as the integrator forms its coefficients.  out: hist_len
+ * host doubles.  Errors: MR_ERR_ARG (tau outside (0,1], order or hist_len out
+ * of range, spacing not positive and finite). */
+int mr_ab_coeffs(int order, int hist_len, double spacing, double tau, double *out);
 
 /* Per-launch timing of the grids' fused right-hand-side kernels with HIP
  * events recorded on the stream each launch is issued on: grid >= 0 times that

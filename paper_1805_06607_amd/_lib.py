@@ -61,7 +61,7 @@ SIGNATURES = {
     "mr_set_macrostep": [c_void_p, c_double],
     "mr_mrab_resume": [c_void_p, c_double],
     "mr_time": [c_void_p, POINTER(c_double), POINTER(c_int64)],
-    "mr_ab_coeffs": [c_int, c_int, c_double, POINTER(c_double)],
+    "mr_ab_coeffs": [c_int, c_int, c_double, c_double, POINTER(c_double)],
     "mr_kernel_timing": [c_void_p, c_int, c_int],
     "mr_kernel_time": [c_void_p, POINTER(c_double), POINTER(c_int)],
     "mr_kernel_time_grid": [c_void_p, c_int, POINTER(c_double), POINTER(c_int)],

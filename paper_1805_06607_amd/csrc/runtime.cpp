@@ -2629,12 +2629,12 @@ int mr_time(const mr_ctx *c, double *t, int64_t *ms)
     return MR_OK;
 }
 
-int mr_ab_coeffs(int order, int hist_len, double tau, double *out)
+int mr_ab_coeffs(int order, int hist_len, double spacing, double tau, double *out)
 {
-    if (!out || !(tau > 0.0) || tau > 1.0) return MR_ERR_ARG;
+    if (!out || !(tau > 0.0) || tau > 1.0 || !(spacing > 0.0) || !std::isfinite(spacing)) return MR_ERR_ARG;
     std::vector<long double> a;
     if (!ab_alpha(order, hist_len, (long double)tau, a)) return MR_ERR_ARG;
-    for (int j = 0; j < hist_len; ++j) out[j] = (double)a[j];
+    for (int j = 0; j < hist_len; ++j) out[j] = (double)a[j] * spacing;
     return MR_OK;
 }
 

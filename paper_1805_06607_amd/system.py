@@ -268,7 +268,8 @@ class System:
             pass
 
 
-def ab_coeffs(order: int, hist_len: int, tau: float = 1.0) -> np.ndarray:
+def ab_coeffs(order: int, hist_len: int, tau: float = 1.0, spacing: float = 1.0) -> np.ndarray:
+    """spacing * alpha_j (oldest first) of mr_ab_coeffs."""
     out = (c_double * hist_len)()
-    _lib.check(_lib.load().mr_ab_coeffs(order, hist_len, tau, out), None, "mr_ab_coeffs")
+    _lib.check(_lib.load().mr_ab_coeffs(order, hist_len, spacing, tau, out), None, "mr_ab_coeffs")
     return np.array(out[:])

@@ -37,6 +37,9 @@ def test_host_ab_coefficients_match_oracle(n, m, tau):
     got = ab_coeffs(n, m, float(tau))
     want = np.array([float(a) for a in ab_coefficients(n, m, tau)])
     np.testing.assert_allclose(got, want, rtol=2e-16, atol=2e-16)
+    # scaled by a step: the rounded coefficient times the step, as the integrator forms it
+    h = 3.7e-4
+    assert np.array_equal(ab_coeffs(n, m, float(tau), spacing=h), got * h)
 
 
 def test_argument_validation_without_device():
@@ -66,6 +69,9 @@ def test_argument_validation_without_device():
     assert lib.mr_finalize(ctx, ctypes.byref(out)) == -2
     assert lib.mr_bind_static_workspace(ctx) == -2                     # before mr_finalize
     assert lib.mr_bind_static_workspace(None) == -1
+    buf = (ctypes.c_double * 3)()
+    assert lib.mr_ab_coeffs(3, 3, 0.0, 1.0, buf) == -1                # spacing must be positive
+    assert lib.mr_ab_coeffs(3, 3, 1.0, 1.5, buf) == -1                # tau outside (0, 1]
     assert lib.mr_save(ctx, ctypes.c_void_p(256), 1 << 20) == -2       # before mr_mrab_start
     assert lib.mr_load(ctx, ctypes.c_void_p(256), 1 << 20) == -2       # before mr_bind_workspace
     assert lib.mr_save(ctx, None, 0) == -1
