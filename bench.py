@@ -197,6 +197,7 @@ def run_batch(args):
     torch.cuda.synchronize()
     el_s = time.perf_counter() - t0
     bpp = 8 * 4 * (3 + 2)
+    rl = batch_roofline(systems, best, tune_ms, bpp)
     line = {"metric": "batched MRAB pt-updates/s (64 uneven systems), 1 GPU", "value": pts * args.steps / el_b,
             "unit": "pt-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": el_b / args.steps * 1e3, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
@@ -207,9 +208,39 @@ def run_batch(args):
             "one_system_at_a_time": {"value": pts * ks / el_s, "ms_per_step": el_s / ks * 1e3},
             "batch_speedup": (el_s / ks) / (el_b / args.steps),
             "algorithmic_GB_per_s": pts * bpp * args.steps / el_b / 1e9,
-            "bytes_per_point": bpp}
+            "bytes_per_point": bpp, "roofline": rl}
     b.close()
     print(json.dumps(line), flush=True)
+
+
+def batch_roofline(systems, shape, tune_ms, bpp):
+    """Roofline of the batch's dominant launch, the one in which every grid of
+    every system takes a fused right-hand side + AB update (all grids
+    Cartesian, one tile shape: one work-list launch): algorithmic bytes
+    (bpp x active points of every grid) / its duration, HIP-event timed by
+    the batch autotuner on the batch's stream (reps passes after a warm-up
+    pass).  Next to it the committed kernel-trace duration and counter
+    traffic of that launch, when taken on the kernels as they are now."""
+    from paper_1805_06607_amd.batch import tile_shape_info
+    if shape < 0 or any(g.kind == 1 for s in systems for g in s.wl.grids):
+        return None
+    tx, ty, tm = tile_shape_info(shape)
+    threads = sum(-(-g.n[0] // tx) * -(-g.n[1] // ty) * tx * ty * tm for s in systems for g in s.wl.grids)
+    key = f"k_rhs_tiles<{int(systems[0].wl.params['sbp'])}, 1, {tx}, {ty}, {tm}> grid={threads}"
+    n_act = sum(int(ib.sum()) for s in systems for ib in s.iblanks)
+    bl = n_act * bpp
+    avg = tune_ms[shape] * 1e-3
+    ach = bl / avg / 1e9
+    out = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+           "traffic": stored_traffic().get(key), "kernel": key, "points": n_act, "bytes_per_point": bpp,
+           "bytes_per_launch": bl, "avg_launch_us": avg * 1e6,
+           "timing": "HIP events around the batch autotuner's timed passes on the batch's stream"}
+    kt = stored_trace().get(key)
+    if kt:
+        out["kernel_trace_us"] = kt
+        out["frac_kernel_trace"] = bl / (kt * 1e-6) / 1e9 / HBM_PEAK_GBS
+        out["kernel_trace_source"] = "profiles/kernel_trace.txt"
+    return out
 
 
 def run_adjoint(args):
@@ -395,7 +426,8 @@ def stored_traffic():
                 ok = ln.split("=", 1)[1].strip() == sha
             elif ln.startswith("k_") and "bytes_per_launch=" in ln:
                 name, val = ln.rsplit("bytes_per_launch=", 1)
-                out[name.split(" grid=")[0].strip()] = float(val)
+                out[name.strip()] = float(val)
+                out.setdefault(name.split(" grid=")[0].strip(), float(val))
             elif ln.startswith("tile3d_pair") and "bytes_per_launch=" in ln:
                 name, val = ln.rsplit("bytes_per_launch=", 1)
                 out[name.strip()] = float(val)

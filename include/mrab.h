@@ -308,6 +308,10 @@ int mr_set_option(mr_ctx *ctx, const char *name, int64_t value);
 enum { MR_NUM_TILE_SHAPES = 8 };
 int mr_set_tile_shape(mr_ctx *ctx, int grid, int shape);
 int mr_get_tile_shape(const mr_ctx *ctx, int grid, int *shape, int *tx, int *ty, int *tm);
+/* The tile of shape `shape` (0..MR_NUM_TILE_SHAPES-1): tx x ty outputs per
+ * workgroup, tm threads per output; host only, no device needed.  Null
+ * output pointers are skipped.  Errors: MR_ERR_ARG (shape out of range). */
+int mr_tile_shape_info(int shape, int *tx, int *ty, int *tm);
 
 /* Autotuner (setup; synchronises): for every 2D grid, time reps launches of
  * each tile shape on the current state, writing only scratch buffers, and

@@ -68,6 +68,7 @@ SIGNATURES = {
     "mr_set_option": [c_void_p, c_char_p, c_int64],
     "mr_set_tile_shape": [c_void_p, c_int, c_int],
     "mr_get_tile_shape": [c_void_p, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_int)],
+    "mr_tile_shape_info": [c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int)],
     "mr_autotune": [c_void_p, c_int],
     "mr_guard": [c_void_p, POINTER(c_double)],
     "mr_batch_create": [POINTER(c_void_p), c_int, POINTER(c_void_p)],

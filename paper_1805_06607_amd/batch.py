@@ -12,6 +12,17 @@ from . import _lib
 from .system import System
 
 
+def tile_shape_info(shape: int):
+    """(tx, ty, tm) of a tile shape: tx x ty outputs per workgroup, tm
+    threads per output."""
+    from ctypes import c_int
+    lib = _lib.load()
+    tx, ty, tm = c_int(), c_int(), c_int()
+    rc = lib.mr_tile_shape_info(shape, byref(tx), byref(ty), byref(tm))
+    _lib.check(rc, None, "mr_tile_shape_info")
+    return tx.value, ty.value, tm.value
+
+
 class Batch:
     def __init__(self, systems: List[System]):
         self.lib = _lib.load()

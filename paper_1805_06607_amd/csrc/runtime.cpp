@@ -2872,6 +2872,16 @@ int mr_get_tile_shape(const mr_ctx *c, int g, int *shape, int *tx, int *ty, int 
     return MR_OK;
 }
 
+int mr_tile_shape_info(int shape, int *tx, int *ty, int *tm)
+{
+    if (shape < 0 || shape >= mrk::NUM_TILE_SHAPES) return MR_ERR_ARG;
+    const mrk::TileShape &t = mrk::kTileShapes[shape];
+    if (tx) *tx = t.tx;
+    if (ty) *ty = t.ty;
+    if (tm) *tm = t.tm;
+    return MR_OK;
+}
+
 int mr_autotune(mr_ctx *c, int reps)
 {
     if (c) c->version++;

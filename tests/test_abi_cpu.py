@@ -97,3 +97,20 @@ def test_library_defines_no_unprefixed_c_functions():
     funcs = [ln.split()[-1] for ln in out.splitlines() if len(ln.split()) == 3 and ln.split()[1] in ("T", "W")]
     bad = [f for f in funcs if not (f.startswith("mr_") or f.startswith("_Z") or f in ("_init", "_fini"))]
     assert not bad, bad
+
+
+def test_tile_shape_table_without_device():
+    """Every tile shape is a whole number of 64-wide wavefronts within one
+    workgroup; the query is host only and rejects shapes out of range."""
+    from paper_1805_06607_amd import _lib
+    from paper_1805_06607_amd.batch import tile_shape_info
+    seen = set()
+    for s in range(_lib.NUM_TILE_SHAPES):
+        tx, ty, tm = tile_shape_info(s)
+        assert tx > 0 and ty > 0 and tm > 0
+        assert (tx * ty * tm) % 64 == 0 and tx * ty * tm <= 1024
+        seen.add((tx, ty, tm))
+    assert len(seen) == _lib.NUM_TILE_SHAPES
+    lib = _lib.load()
+    for bad in (-1, _lib.NUM_TILE_SHAPES):
+        assert _lib.STATUS[lib.mr_tile_shape_info(bad, None, None, None)] == "MR_ERR_ARG"
