@@ -57,7 +57,8 @@ enum { MR_CARTESIAN = 0, MR_CURVILINEAR = 1 };
  *  order, hist_len  AB order n and history length m >= n (m > n: the
  *                 extended-history, minimum-norm schemes of eq. ext_ab).
  *  interp_width   donor stencil width per direction (2 bilinear, 4 cubic);
- *                 informational, the weights come with mr_set_overset.
+ *                 informational, the weights come with mr_set_overset or
+ *                 mr_assemble_overset (whose width argument rules).
  *  gamma, Re, Pr, mu, lambda_over_mu  gas constants; T = p/rho,
  *                 c_p = gamma/(gamma-1), tau_ij as in the Appendix equations.
  *  sigma_I_iface  sigma^I of the SAT interface penalty, eq. (int) (1/2).
@@ -120,6 +121,43 @@ int mr_add_grid(mr_ctx *ctx, const mr_grid_desc *desc, int *grid_id);
  * Errors: MR_ERR_ARG (index out of range), MR_ERR_SETUP (donor point blanked). */
 int mr_set_overset(mr_ctx *ctx, int recv_grid, int donor_grid, int64_t n, int stencil_size,
                    const int64_t *recv_pt, const int64_t *donor_pt, const double *weights);
+
+/* Fractional-index callback for mr_assemble_overset: for the n physical
+ * points x (dim x n doubles, component-major), write their fractional indices
+ * in curvilinear grid `grid` to f (dim x n; grid point i of a direction sits
+ * at i; NaN marks a point outside the grid).  Return 0, or nonzero to abort
+ * the assembly. */
+typedef int (*mr_locate_fn)(void *user, int grid, int64_t n, const double *x, double *f);
+
+/* Chimera donor-receiver search and interpolation weights for every grid, in
+ * place of mr_set_overset calls (section "SAT-Based Interpolation": donor
+ * search, then Lagrange interpolation with weights from Lagrange shape
+ * functions).  Receivers are the active points that end a run on an
+ * interface face.  For each receiver, the donor is the first other grid in
+ * decreasing priority[grid] (ties: lower id) whose width-point-per-direction
+ * stencil, based at floor(f) - (width/2 - 1) around the receiver's fractional
+ * index f, lies inside the grid (periodic directions wrap) and covers only
+ * active points; weights are tensor products of the 1D Lagrange shape
+ * functions on the width integer nodes (entry order x fastest).  Fractional
+ * indices: on Cartesian grids (x - origin) / spacing; on curvilinear grids
+ * the caller's locate (user is passed through), or with locate == NULL the
+ * library's own search (the nearest grid point, then Newton iterations on the
+ * grid's coordinates interpolated by 4-point Lagrange polynomials per
+ * direction).  Receivers register grid by grid, per grid donor by donor in
+ * priority order, ascending point order within a pair (mr_get_overset reads
+ * them back).  Host only.
+ * Errors: MR_ERR_ARG (width, stencil above 64 points), MR_ERR_STATE (after
+ * mr_finalize, receivers already registered), MR_ERR_SETUP (a receiver
+ * without a donor, the callback failed). */
+int mr_assemble_overset(mr_ctx *ctx, int width, const int *priority, mr_locate_fn locate, void *user);
+
+/* The registered donor stencils of grid's receivers, in row order: with every
+ * array NULL, *n is set to the number of receivers; otherwise *n must be at
+ * least that number and is set to it, recv_pt[n], donor_grid[n],
+ * donor_pt[n*S] and weights[n*S] (S = stencil size; any may be NULL) are
+ * filled.  Host only.  Errors: MR_ERR_ARG (bad grid, *n too small). */
+int mr_get_overset(const mr_ctx *ctx, int grid, int64_t *n, int64_t *recv_pt, int *donor_grid, int64_t *donor_pt,
+                   double *weights);
 
 /* Validate (every interface run end has exactly one donor stencil, every rate
  * divides the largest), build the device tables and the static rate schedule,

@@ -34,6 +34,10 @@ class MrGridDesc(ctypes.Structure):
     ]
 
 
+# mr_locate_fn of mrab.h
+LOCATE_FN = ctypes.CFUNCTYPE(c_int, c_void_p, c_int, c_int64, POINTER(c_double), POINTER(c_double))
+
+
 class MrabError(RuntimeError):
     pass
 
@@ -44,6 +48,9 @@ SIGNATURES = {
     "mr_create": [POINTER(MrParams), c_void_p, POINTER(c_void_p)],
     "mr_add_grid": [c_void_p, POINTER(MrGridDesc), POINTER(c_int)],
     "mr_set_overset": [c_void_p, c_int, c_int, c_int64, c_int, POINTER(c_int64), POINTER(c_int64),
+                       POINTER(c_double)],
+    "mr_assemble_overset": [c_void_p, c_int, POINTER(c_int), LOCATE_FN, c_void_p],
+    "mr_get_overset": [c_void_p, c_int, POINTER(c_int64), POINTER(c_int64), POINTER(c_int), POINTER(c_int64),
                        POINTER(c_double)],
     "mr_finalize": [c_void_p, POINTER(c_size_t)],
     "mr_bind_workspace": [c_void_p, c_void_p, c_size_t],

@@ -2136,6 +2136,156 @@ int adj_upload_objective(mr_ctx *c)
 }  // namespace
 
 // =================================================================== C ABI
+namespace {
+
+// ---------------------------------------------------------------------------
+// Chimera donor-receiver search (section "SAT-Based Interpolation": donor
+// search, Lagrange interpolation weights from Lagrange shape functions)
+// ---------------------------------------------------------------------------
+
+// physical position of point p of grid g
+void point_position(const GridHost &g, int64_t p, double *x)
+{
+    if (g.kind == MR_CURVILINEAR) {
+        for (int c = 0; c < g.dim; ++c) x[c] = g.coords[(size_t)c * g.npts + p];
+        return;
+    }
+    int64_t r = p;
+    for (int d = 0; d < g.dim; ++d) {
+        const int64_t i = r % g.n[d];
+        r /= g.n[d];
+        x[d] = g.origin[d] + g.spacing[d] * (double)i;
+    }
+}
+
+// coordinates of the (possibly out-of-range, periodic) index i[] of a
+// curvilinear grid: wrapped, plus the coordinate jump of each seam crossed
+void curv_coord(const GridHost &g, const int64_t *i, double *x)
+{
+    int64_t p = 0;
+    double shift[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < g.dim; ++d) {
+        int64_t k = i[d];
+        if (g.periodic[d]) {
+            const int64_t w = ((k % g.n[d]) + g.n[d]) % g.n[d];
+            const int64_t turns = (k - w) / g.n[d];
+            for (int c = 0; c < g.dim; ++c) shift[c] += (double)turns * g.coord_period[d][c];
+            k = w;
+        }
+        p += k * g.stride[d];
+    }
+    for (int c = 0; c < g.dim; ++c) x[c] = g.coords[(size_t)c * g.npts + p] + shift[c];
+}
+
+// 1D Lagrange shape functions of the nodes 0..W-1 at t, and their derivatives
+void lagrange_shape(double t, int W, double *L, double *dL)
+{
+    for (int a = 0; a < W; ++a) {
+        double v = 1.0, dv = 0.0;
+        for (int b = 0; b < W; ++b) {
+            if (b == a) continue;
+            const double f = (t - b) / (double)(a - b);
+            dv = dv * f + v / (double)(a - b);
+            v *= f;
+        }
+        L[a] = v;
+        if (dL) dL[a] = dv;
+    }
+}
+
+// fractional index of x in curvilinear grid g, the library's own search: the
+// nearest grid point starts a Newton iteration on the grid's coordinates
+// interpolated by 4-point (fewer on short non-periodic lines) Lagrange
+// polynomials per direction; false when it does not converge
+bool locate_curvilinear(const GridHost &g, const double *x, double *f)
+{
+    const int dim = g.dim;
+    int64_t best = 0;
+    double bd = INFINITY;
+    for (int64_t p = 0; p < g.npts; ++p) {
+        double d2 = 0.0;
+        for (int c = 0; c < dim; ++c) {
+            const double e = g.coords[(size_t)c * g.npts + p] - x[c];
+            d2 += e * e;
+        }
+        if (d2 < bd) {
+            bd = d2;
+            best = p;
+        }
+    }
+    double s[3];
+    for (int d = 0; d < dim; ++d) s[d] = (double)((best / g.stride[d]) % g.n[d]);
+    int W[3];
+    for (int d = 0; d < dim; ++d) W[d] = g.periodic[d] ? 4 : std::min(4, g.n[d]);
+    int polish = -1;
+    for (int it = 0; it < 60; ++it) {
+        int64_t base[3];
+        double L[3][4], dL[3][4];
+        for (int d = 0; d < dim; ++d) {
+            base[d] = (int64_t)std::floor(s[d]) - (W[d] / 2 - 1);
+            if (!g.periodic[d]) base[d] = std::min<int64_t>(std::max<int64_t>(base[d], 0), g.n[d] - W[d]);
+            lagrange_shape(s[d] - (double)base[d], W[d], L[d], dL[d]);
+        }
+        double X[3] = {0, 0, 0}, J[3][3] = {{0}};
+        const int ne = dim == 2 ? W[0] * W[1] : W[0] * W[1] * W[2];
+        for (int e = 0; e < ne; ++e) {
+            int a[3] = {e % W[0], (e / W[0]) % W[1], dim == 3 ? e / (W[0] * W[1]) : 0};
+            int64_t idx[3];
+            for (int d = 0; d < dim; ++d) idx[d] = base[d] + a[d];
+            double xc[3];
+            curv_coord(g, idx, xc);
+            double w = 1.0, dw[3];
+            for (int d = 0; d < dim; ++d) w *= L[d][a[d]];
+            for (int k = 0; k < dim; ++k) {
+                dw[k] = 1.0;
+                for (int d = 0; d < dim; ++d) dw[k] *= d == k ? dL[d][a[d]] : L[d][a[d]];
+            }
+            for (int c = 0; c < dim; ++c) {
+                X[c] += w * xc[c];
+                for (int k = 0; k < dim; ++k) J[c][k] += dw[k] * xc[c];
+            }
+        }
+        // Newton step: solve J step = X - x (Gaussian elimination, partial pivoting)
+        double A[3][4];
+        for (int c = 0; c < dim; ++c) {
+            for (int k = 0; k < dim; ++k) A[c][k] = J[c][k];
+            A[c][dim] = X[c] - x[c];
+        }
+        for (int k = 0; k < dim; ++k) {
+            int piv = k;
+            for (int c = k + 1; c < dim; ++c)
+                if (std::fabs(A[c][k]) > std::fabs(A[piv][k])) piv = c;
+            if (!(std::fabs(A[piv][k]) > 0.0)) return false;
+            if (piv != k)
+                for (int j = 0; j <= dim; ++j) std::swap(A[k][j], A[piv][j]);
+            for (int c = k + 1; c < dim; ++c) {
+                const double m = A[c][k] / A[k][k];
+                for (int j = k; j <= dim; ++j) A[c][j] -= m * A[k][j];
+            }
+        }
+        double step[3], big = 0.0;
+        for (int k = dim - 1; k >= 0; --k) {
+            double v = A[k][dim];
+            for (int j = k + 1; j < dim; ++j) v -= A[k][j] * step[j];
+            step[k] = v / A[k][k];
+            big = std::max(big, std::fabs(step[k]));
+        }
+        for (int d = 0; d < dim; ++d) s[d] -= step[d];
+        for (int d = 0; d < dim; ++d)
+            if (!std::isfinite(s[d]) || std::fabs(s[d]) > 4.0 * g.n[d] + 8.0) return false;
+        if (polish > 0 && --polish == 0) break;
+        if (polish < 0 && big < 1e-12) polish = 2;   // two more steps at the rounding floor
+        if (it == 59) return false;
+    }
+    for (int d = 0; d < dim; ++d) {
+        if (g.periodic[d]) s[d] = s[d] - std::floor(s[d] / g.n[d]) * g.n[d];
+        f[d] = s[d];
+    }
+    return true;
+}
+
+}  // namespace
+
 extern "C" {
 
 int mr_create(const mr_params *params, void *hip_stream, mr_ctx **out)
@@ -2245,6 +2395,154 @@ int mr_set_overset(mr_ctx *c, int rg, int dg, int64_t n, int S, const int64_t *r
         }
     }
     if (n) c->links.push_back(L);
+    return MR_OK;
+}
+
+
+int mr_assemble_overset(mr_ctx *c, int W, const int *priority, mr_locate_fn locate, void *user)
+{
+    if (!c || !priority) return MR_ERR_ARG;
+    if (c->finalized) return fail(c, MR_ERR_STATE, "mr_assemble_overset after mr_finalize");
+    if (W < 1 || W > 8) return fail(c, MR_ERR_ARG, "stencil width must be 1..8");
+    const int G = (int)c->G.size();
+    if (G == 0) return fail(c, MR_ERR_STATE, "no grids");
+    const int dim = c->P.dim;
+    int S = 1;
+    for (int d = 0; d < dim; ++d) S *= W;
+    if (S > 64) return fail(c, MR_ERR_ARG, "stencil of more than 64 points");
+    for (const GridHost &g : c->G)
+        for (int64_t p = 0; p < g.npts; ++p)
+            if (g.recv_idx[p] >= 0) return fail(c, MR_ERR_STATE, "receivers already registered");
+    std::vector<int> order(G);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return priority[a] > priority[b]; });
+    for (int g = 0; g < G; ++g) {
+        const GridHost &R = c->G[g];
+        std::vector<int64_t> recv;
+        for (int64_t p = 0; p < R.npts; ++p)
+            if (R.iblank[p] && is_iface(R, p)) recv.push_back(p);
+        const int64_t nr = (int64_t)recv.size();
+        std::vector<double> X((size_t)dim * nr);
+        for (int64_t r = 0; r < nr; ++r) {
+            double x[3];
+            point_position(R, recv[r], x);
+            for (int k = 0; k < dim; ++k) X[(size_t)k * nr + r] = x[k];
+        }
+        std::vector<char> todo(nr, 1);
+        int64_t left = nr;
+        for (int dg : order) {
+            if (dg == g || left == 0) continue;
+            const GridHost &D = c->G[dg];
+            std::vector<int64_t> sel;
+            for (int64_t r = 0; r < nr; ++r)
+                if (todo[r]) sel.push_back(r);
+            const int64_t ns = (int64_t)sel.size();
+            std::vector<double> xs((size_t)dim * ns), fs((size_t)dim * ns, NAN);
+            for (int64_t k = 0; k < ns; ++k)
+                for (int d = 0; d < dim; ++d) xs[(size_t)d * ns + k] = X[(size_t)d * nr + sel[k]];
+            if (D.kind == MR_CARTESIAN) {
+                for (int64_t k = 0; k < ns; ++k)
+                    for (int d = 0; d < dim; ++d)
+                        fs[(size_t)d * ns + k] = (xs[(size_t)d * ns + k] - D.origin[d]) / D.spacing[d];
+            } else if (locate) {
+                if (locate(user, dg, ns, xs.data(), fs.data()) != 0)
+                    return fail(c, MR_ERR_SETUP, "the locate callback failed for donor grid %d", dg);
+            } else {
+                for (int64_t k = 0; k < ns; ++k) {
+                    double x[3], f[3];
+                    for (int d = 0; d < dim; ++d) x[d] = xs[(size_t)d * ns + k];
+                    if (locate_curvilinear(D, x, f))
+                        for (int d = 0; d < dim; ++d) fs[(size_t)d * ns + k] = f[d];
+                }
+            }
+            std::vector<int64_t> hit_r, hit_p;
+            std::vector<double> hit_w;
+            for (int64_t k = 0; k < ns; ++k) {
+                bool ok = true;
+                int64_t ids[3][8];
+                double w1[3][8];
+                for (int d = 0; d < dim && ok; ++d) {
+                    const double f = fs[(size_t)d * ns + k];
+                    if (!std::isfinite(f)) {
+                        ok = false;
+                        break;
+                    }
+                    const int64_t b = (int64_t)std::floor(f) - (W / 2 - 1);
+                    if (!D.periodic[d] && (b < 0 || b + W - 1 > D.n[d] - 1)) {
+                        ok = false;
+                        break;
+                    }
+                    for (int a = 0; a < W; ++a) {
+                        int64_t i = b + a;
+                        if (D.periodic[d]) i = ((i % D.n[d]) + D.n[d]) % D.n[d];
+                        ids[d][a] = i;
+                    }
+                    // shape function a: the product over b != a of (s - b) / (a - b)
+                    const double s = f - (double)b;
+                    for (int a = 0; a < W; ++a) {
+                        double v = 1.0;
+                        for (int bb = 0; bb < W; ++bb)
+                            if (bb != a) v *= (s - (double)bb) / (double)(a - bb);
+                        w1[d][a] = v;
+                    }
+                }
+                if (!ok) continue;
+                int64_t pts[64];
+                double wts[64];
+                for (int e = 0; e < S && ok; ++e) {
+                    int64_t q = 0;
+                    double w = 1.0;
+                    int rest = e;
+                    for (int d = 0; d < dim; ++d) {
+                        const int a = rest % W;
+                        rest /= W;
+                        q += ids[d][a] * D.stride[d];
+                        w *= w1[d][a];
+                    }
+                    if (!D.iblank[q]) ok = false;
+                    pts[e] = q;
+                    wts[e] = w;
+                }
+                if (!ok) continue;
+                hit_r.push_back(recv[sel[k]]);
+                hit_p.insert(hit_p.end(), pts, pts + S);
+                hit_w.insert(hit_w.end(), wts, wts + S);
+                todo[sel[k]] = 0;
+                --left;
+            }
+            if (!hit_r.empty()) {
+                int rc = mr_set_overset(c, g, dg, (int64_t)hit_r.size(), S, hit_r.data(), hit_p.data(), hit_w.data());
+                if (rc) return rc;
+            }
+        }
+        if (left) return fail(c, MR_ERR_SETUP, "grid %d: %lld receivers without a donor", g, (long long)left);
+    }
+    return MR_OK;
+}
+
+int mr_get_overset(const mr_ctx *c, int g, int64_t *n, int64_t *recv_pt, int *donor_grid, int64_t *donor_pt,
+                   double *weights)
+{
+    if (!c || !n || g < 0 || g >= (int)c->G.size()) return MR_ERR_ARG;
+    const GridHost &R = c->G[g];
+    const int64_t k = (int64_t)R.recv_pts.size();
+    if (!recv_pt && !donor_grid && !donor_pt && !weights) {
+        *n = k;
+        return MR_OK;
+    }
+    if (*n < k) return MR_ERR_ARG;
+    const int S = c->S ? c->S : 1;
+    for (size_t r = 0; r < c->rgrid.size(); ++r) {
+        if (c->rgrid[r] != g) continue;
+        const int32_t row = c->rrow[r];
+        if (recv_pt) recv_pt[row] = R.recv_pts[row];
+        if (donor_grid) donor_grid[row] = c->egrid[r * S];
+        for (int e = 0; e < S; ++e) {
+            if (donor_pt) donor_pt[(int64_t)row * S + e] = c->ept[r * S + e];
+            if (weights) weights[(int64_t)row * S + e] = c->ew[r * S + e];
+        }
+    }
+    *n = k;
     return MR_OK;
 }
 

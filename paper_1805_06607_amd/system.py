@@ -38,25 +38,33 @@ def _params(wl) -> _lib.MrParams:
     return p
 
 
-class System:
-    """An overset problem assembled on the GPU.
+class HostSetup:
+    """A problem's host-side setup through the C ABI (no device touched):
+    context, grids (blanking from the problem's hole shapes), the library's
+    donor search and weights; the receiver rows and donor stencils read back.
+    ``stream`` is a hipStream_t handle (None: the default stream).  With
+    ``own_locate`` the library locates points in curvilinear grids by its own
+    search instead of the problem's closed-form inverse map."""
 
-    ``wl`` is a problem description (see the ``workloads`` package): grids,
-    boundary flags, hole shapes, rates, parameters and initial states.
-    """
-
-    def __init__(self, wl, device: str = "cuda:0", stream: Optional[torch.cuda.Stream] = None,
-                 static_workspace: bool = False):
+    def __init__(self, wl, stream=None, own_locate: bool = False):
+        self.own_locate = own_locate
         self.lib = _lib.load()
         self.wl = wl
-        self.device = torch.device(device)
-        self.dim, self.nv = wl.dim, wl.dim + 2
-        self.RB = self.nv + self.dim * (self.nv - 1)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.dim = wl.dim
         self._params = _params(wl)
         self.ctx = c_void_p()
-        _lib.check(self.lib.mr_create(byref(self._params), c_void_p(self.stream.cuda_stream), byref(self.ctx)),
-                   None, "mr_create")
+        _lib.check(self.lib.mr_create(byref(self._params), c_void_p(stream), byref(self.ctx)), None, "mr_create")
+        try:
+            self._grids_and_overset(wl)
+        except Exception:
+            self.lib.mr_destroy(self.ctx)
+            self.ctx = c_void_p()
+            raise
+
+    def _check(self, rc, what):
+        _lib.check(rc, self.ctx, what)
+
+    def _grids_and_overset(self, wl):
         self.iblanks = []
         self._keep = []
         for g in wl.grids:
@@ -84,26 +92,73 @@ class System:
             d.rate = g.rate
             gid = c_int()
             self._check(self.lib.mr_add_grid(self.ctx, byref(d), byref(gid)), "mr_add_grid")
+
+        # donor search and weights in the library; curvilinear grids located
+        # by the problem description's closed-form inverse map (or the
+        # library's own search)
         W = int(wl.params["interp_width"])
-        self.recv_pts = [assemble.receivers(g, ib) for g, ib in zip(wl.grids, self.iblanks)]
-        self.donor_tables = assemble.donors(wl.grids, self.iblanks, self.recv_pts, W)
+        dim = self.dim
+
+        def locate(_user, grid, n, x, f):
+            try:
+                if n > 0:
+                    X = np.ctypeslib.as_array(x, shape=(dim * n,)).reshape(dim, n)
+                    out = np.ctypeslib.as_array(f, shape=(dim * n,))
+                    out[:] = np.asarray(wl.grids[grid].frac_index(X), dtype=np.float64).reshape(-1)
+                return 0
+            except Exception:
+                return 1
+
+        self._locate = _lib.LOCATE_FN() if self.own_locate else _lib.LOCATE_FN(locate)
+        prio = (c_int * len(wl.grids))(*[int(g.priority) for g in wl.grids])
+        self._check(self.lib.mr_assemble_overset(self.ctx, W, prio, self._locate, None), "mr_assemble_overset")
         S = W ** self.dim
-        for g, tab in enumerate(self.donor_tables):
-            for dg, (rp, pts, w) in tab.items():
-                rp = np.ascontiguousarray(rp, dtype=np.int64)
-                pts = np.ascontiguousarray(pts, dtype=np.int64)
-                w = np.ascontiguousarray(w, dtype=np.float64)
-                self._check(self.lib.mr_set_overset(self.ctx, g, dg, len(rp), S,
-                                                     rp.ctypes.data_as(POINTER(c_int64)),
-                                                     pts.ctypes.data_as(POINTER(c_int64)),
-                                                     w.ctypes.data_as(POINTER(c_double))), "mr_set_overset")
-        # receiver row order inside the library: registration order
-        self.recv_order = []
-        for g, tab in enumerate(self.donor_tables):
-            order = []
-            for dg, (rp, _, _) in tab.items():
-                order.extend(rp.tolist())
-            self.recv_order.append(np.array(order, dtype=np.int64))
+        # the library's receiver rows (registration order) and donor stencils
+        self.recv_pts, self.donor_tables, self.recv_order = [], [], []
+        for g in range(len(wl.grids)):
+            n = c_int64()
+            self._check(self.lib.mr_get_overset(self.ctx, g, byref(n), None, None, None, None), "mr_get_overset")
+            k = int(n.value)
+            rp = np.zeros(max(k, 1), dtype=np.int64)
+            dg = np.zeros(max(k, 1), dtype=np.int32)
+            pts = np.zeros(max(k, 1) * S, dtype=np.int64)
+            w = np.zeros(max(k, 1) * S, dtype=np.float64)
+            self._check(self.lib.mr_get_overset(self.ctx, g, byref(n), rp.ctypes.data_as(POINTER(c_int64)),
+                                                dg.ctypes.data_as(POINTER(c_int)),
+                                                pts.ctypes.data_as(POINTER(c_int64)),
+                                                w.ctypes.data_as(POINTER(c_double))), "mr_get_overset")
+            rp, dg, pts, w = rp[:k], dg[:k], pts[:k * S].reshape(k, S), w[:k * S].reshape(k, S)
+            self.recv_order.append(rp.copy())
+            self.recv_pts.append(np.sort(rp))
+            tab = {}
+            for d in dict.fromkeys(dg.tolist()):
+                sel = dg == d
+                tab[int(d)] = (rp[sel], pts[sel], w[sel])
+            self.donor_tables.append(tab)
+
+
+class System:
+    """An overset problem assembled on the GPU.
+
+    ``wl`` is a problem description (see the ``workloads`` package): grids,
+    boundary flags, hole shapes, rates, parameters and initial states.
+    """
+
+    def __init__(self, wl, device: str = "cuda:0", stream: Optional[torch.cuda.Stream] = None,
+                 static_workspace: bool = False):
+        self.lib = _lib.load()
+        self.wl = wl
+        self.device = torch.device(device)
+        self.dim, self.nv = wl.dim, wl.dim + 2
+        self.RB = self.nv + self.dim * (self.nv - 1)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._host = HostSetup(wl, self.stream.cuda_stream)
+        self.ctx = self._host.ctx
+        self._params = self._host._params
+        self.iblanks = self._host.iblanks
+        self.recv_pts = self._host.recv_pts
+        self.donor_tables = self._host.donor_tables
+        self.recv_order = self._host.recv_order
         nbytes = c_size_t()
         self._check(self.lib.mr_finalize(self.ctx, byref(nbytes)), "mr_finalize")
         self.workspace_bytes = int(nbytes.value)

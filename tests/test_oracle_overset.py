@@ -202,38 +202,112 @@ def test_curvilinear_donor_weights_reproduce_index_polynomials_and_location():
     assert n_checked > 100
 
 
-@pytest.mark.parametrize("size", ["small", "full"])
-def test_donor_tables_agree_with_product_assembly(size):
-    """The oracle's donor search (its own location, loops) and the product's
-    (closed-form inverse, whole-array numpy) give the same receivers, the
-    same donor grids and the same interpolation weights (as sparse vectors
-    over donor points, so that a stencil base shifted at a node would still
-    compare) on the cylinder."""
-    from paper_1805_06607_amd import assemble
-    wl = (workloads.cylinder(nbg=128, ntheta=96, nr=48) if size == "small"
-          else workloads.cylinder())
+def _sparse(pts, wts):
+    a = {}
+    for q, w in zip(pts, wts):
+        a[int(q)] = a.get(int(q), 0.0) + w
+    return a
+
+
+@pytest.mark.parametrize("case", ["cylinder_small", "cylinder", "vortex_box", "tgv3d_small", "vortex_convergence"])
+def test_donor_tables_agree_with_product_assembly(case):
+    """The oracle's donor search (its own location, loops) and the library's
+    (mr_assemble_overset, host only: runs here without a device; curvilinear
+    grids located by the problem's closed-form inverse) give the same
+    blanking, the same receivers, the same donor grids and the same
+    interpolation weights (as sparse vectors over donor points, so that a
+    stencil base shifted at a node would still compare)."""
+    from paper_1805_06607_amd.system import HostSetup
+    wl = {"cylinder_small": lambda: workloads.cylinder(nbg=128, ntheta=96, nr=48),
+          "cylinder": lambda: workloads.cylinder(),
+          "vortex_box": lambda: workloads.vortex_box(),
+          "tgv3d_small": lambda: workloads.tgv3d(nbg=48, npatch=24, ninner=16),
+          "vortex_convergence": lambda: workloads.vortex_convergence(50)}[case]()
     s = OracleSystem(wl)
-    ibs = [assemble.iblank(g) for g in wl.grids]
-    recs = [assemble.receivers(g, ib) for g, ib in zip(wl.grids, ibs)]
-    prod = assemble.donors(wl.grids, ibs, recs, wl.params["interp_width"])
-    for g in range(len(wl.grids)):
-        assert np.array_equal(s.grids[g].iblank, ibs[g])
-        assert np.array_equal(s.grids[g].recv_pts, recs[g])
-        pmap = {}
-        for dg, (rr, pp, ww) in prod[g].items():
-            for k in range(len(rr)):
-                pmap[int(rr[k])] = (dg, pp[k], ww[k])
-        for r, p in enumerate(s.grids[g].recv_pts):
-            dg, pts, wts = s.donor_tables[g][r]
-            pdg, ppts, pw = pmap[int(p)]
-            assert dg == pdg
-            a, b = {}, {}
-            for q, w in zip(pts, wts):
-                a[int(q)] = a.get(int(q), 0.0) + w
-            for q, w in zip(ppts, pw):
-                b[int(q)] = b.get(int(q), 0.0) + w
-            for k in set(a) | set(b):
-                assert abs(a.get(k, 0.0) - b.get(k, 0.0)) < 1e-12, (g, p, k)
+    h = HostSetup(wl)
+    try:
+        for g in range(len(wl.grids)):
+            assert np.array_equal(s.grids[g].iblank, h.iblanks[g])
+            assert np.array_equal(s.grids[g].recv_pts, h.recv_pts[g])
+            pmap = {}
+            for dg, (rr, pp, ww) in h.donor_tables[g].items():
+                for k in range(len(rr)):
+                    pmap[int(rr[k])] = (dg, pp[k], ww[k])
+            assert len(pmap) == len(s.grids[g].recv_pts)
+            for r, p in enumerate(s.grids[g].recv_pts):
+                dg, pts, wts = s.donor_tables[g][r]
+                pdg, ppts, pw = pmap[int(p)]
+                assert dg == pdg
+                a, b = _sparse(pts, wts), _sparse(ppts, pw)
+                for k in set(a) | set(b):
+                    assert abs(a.get(k, 0.0) - b.get(k, 0.0)) < 1e-12, (g, p, k)
+    finally:
+        h.lib.mr_destroy(h.ctx)
+
+
+@pytest.mark.parametrize("ntheta,nr", [(96, 48), (256, 128)])
+def test_library_own_locate_reproduces_receiver_positions(ntheta, nr):
+    """The library's own search on a curvilinear donor (no inverse map given)
+    inverts the donor's coordinates as interpolated by cubic Lagrange
+    polynomials, the interpolation the cubic (width 4) stencils then apply:
+    interpolating the donor's coordinates with a receiver's weights gives the
+    receiver's position to rounding (Lagrange weights sum to one and
+    reproduce the interpolant).  Against the closed-form inverse of the
+    O-mesh's mapping, the weights differ only by the cubic interpolant's
+    geometric error, which falls at fourth order with the O-mesh's spacing:
+    the same donor points, weight differences below C * (1/ntheta)^4."""
+    from paper_1805_06607_amd.system import HostSetup
+    wl = workloads.cylinder(nbg=2 * ntheta, ntheta=ntheta, nr=nr)
+    own = HostSetup(wl, own_locate=True)
+    ref = HostSetup(wl)
+    try:
+        X = [gr.points() for gr in wl.grids]
+        n_checked = 0
+        for g in range(len(wl.grids)):
+            assert np.array_equal(own.recv_order[g], ref.recv_order[g])
+            for dg, (rr, pp, ww) in own.donor_tables[g].items():
+                rr2, pp2, ww2 = ref.donor_tables[g][dg]
+                assert np.array_equal(rr, rr2) and np.array_equal(pp, pp2)
+                if wl.grids[dg].kind == workloads.CURVILINEAR:
+                    xi = np.einsum("ks,dks->dk", ww, X[dg][:, pp])
+                    err = np.max(np.abs(xi - X[g][:, rr]))
+                    assert err < 1e-12, (g, dg, err)
+                    dw = np.max(np.abs(ww - ww2))
+                    assert 0 < dw < 0.1 * (100.0 / ntheta) ** 4, (g, dg, dw)
+                    n_checked += len(rr)
+                else:
+                    assert np.array_equal(ww, ww2)
+        assert n_checked > 30
+    finally:
+        own.lib.mr_destroy(own.ctx)
+        ref.lib.mr_destroy(ref.ctx)
+
+
+def test_assembly_errors():
+    """A receiver no grid can serve and a failing locate callback are setup
+    errors; receivers cannot be registered twice."""
+    import ctypes
+    from paper_1805_06607_amd import _lib
+    from paper_1805_06607_amd.system import HostSetup
+    wl = workloads.vortex_box()
+    h = HostSetup(wl)
+    lib = h.lib
+    try:
+        prio = (ctypes.c_int * 2)(0, 1)
+        assert _lib.STATUS[lib.mr_assemble_overset(h.ctx, 4, prio, _lib.LOCATE_FN(), None)] == "MR_ERR_STATE"
+    finally:
+        lib.mr_destroy(h.ctx)
+    # the background's hole grown past the patch: no receiver has a donor
+    wl = workloads.vortex_box()
+    c, hb = 5.0, 0.5 * 31 * (10.0 / 128) + 2 * (10.0 / 64)
+    wl.grids[0].holes = [("box", (c - hb, c - hb), (c + hb, c + hb))]
+    with pytest.raises(_lib.MrabError, match="without a donor"):
+        HostSetup(wl)
+    # a locate callback that fails
+    wl = workloads.cylinder(nbg=128, ntheta=96, nr=48)
+    wl.grids[1].inverse = None
+    with pytest.raises(_lib.MrabError, match="locate callback failed"):
+        HostSetup(wl)
 
 
 @pytest.mark.parametrize("case", ["vortex_box", "cylinder_small", "tgv3d_small"])
