@@ -1330,11 +1330,30 @@ __device__ __forceinline__ void donor_block_body(const DonorLink &a, const Donor
             for (int hh = 0; hh < MAXH; ++hh) bj[hh] = a.beta[jj][hh];
         }
     const int64_t N = a.g.npts;
+    // loads that depend on nothing the work computes are issued first: this
+    // lane's receiver entry (weight, row of its donor point), the chunk's
+    // ranges, then this lane's distinct donor point (a chunk has at most 256,
+    // one per lane) and its stencil positions
+    const int kk = tid / a.S, e = tid - kk * a.S;
+    const int64_t k = (int64_t)ch * b.rpc + kk;
+    const bool ok = tid < NT && kk < b.rpc && k < a.nrecv;
+    double w_ent = 0.0;
+    int el_ent = 0;
+    if (ok) {
+        const int64_t ent = k * a.S + e;
+        w_ent = a.w[ent];
+        el_ent = b.eloc[ent];
+    }
     const int u0 = b.ustart[ch], nu = b.ustart[ch + 1] - u0;
+    const bool own_u = tid < NT && tid < nu;
+    const int64_t p_own = own_u ? b.upts[u0 + tid] : 0;
     int c0 = 0, nc = 0;
     if constexpr (EXT) {
         c0 = b.cstart[ch];
         nc = b.cstart[ch + 1] - c0;
+        int16_t bp[KP];
+#pragma unroll
+        for (int r = 0; r < KP; ++r) bp[r] = own_u ? b.bpos[(size_t)(u0 + tid) * KP + r] : (int16_t)0;
         const int mh = a.m;
         // batches of XB items per thread: every load of a batch is issued
         // before the first sum
@@ -1367,7 +1386,9 @@ __device__ __forceinline__ void donor_block_body(const DonorLink &a, const Donor
                 sQ[(size_t)v * b.maxc + ii] = acc;
             }
         }
-        for (int i = tid; tid < NT && i < nu * KP; i += NT) sP[i] = b.bpos[(size_t)u0 * KP + i];
+        if (own_u)
+#pragma unroll
+            for (int r = 0; r < KP; ++r) sP[(size_t)tid * KP + r] = bp[r];
         __syncthreads();
     }
     // EXT: the point's own entry, then its gradient stencil in the order
@@ -1385,8 +1406,9 @@ __device__ __forceinline__ void donor_block_body(const DonorLink &a, const Donor
             for (int v = 0; v < NV; ++v) o[v] = y[v * N + idx];
         }
     };
-    for (int u = tid; tid < NT && u < nu; u += NT) {
-        const int64_t p = b.upts[u0 + u];
+    if (own_u) {
+        const int u = tid;
+        const int64_t p = p_own;
         pos = sP + (size_t)u * KP;
         cursor = 0;
         double qp[NV];
@@ -1417,16 +1439,11 @@ __device__ __forceinline__ void donor_block_body(const DonorLink &a, const Donor
             for (int v = 1; v < NV; ++v) o[NV + d * (NV - 1) + (v - 1)] = Fv[d][v - 1];
     }
     __syncthreads();
-    const int kk = tid / a.S, e = tid - kk * a.S;
-    const int64_t k = (int64_t)ch * b.rpc + kk;
-    const bool ok = tid < NT && kk < b.rpc && k < a.nrecv;
     double val[RB];
     if (ok) {
-        const int64_t ent = k * a.S + e;
-        const double w = a.w[ent];
-        const double *vrow = sV + (size_t)b.eloc[ent] * RB;
+        const double *vrow = sV + (size_t)el_ent * RB;
 #pragma unroll
-        for (int t = 0; t < RB; ++t) val[t] = w * vrow[t];
+        for (int t = 0; t < RB; ++t) val[t] = w_ent * vrow[t];
     } else {
 #pragma unroll
         for (int t = 0; t < RB; ++t) val[t] = 0.0;
@@ -1493,11 +1510,12 @@ k_rhs_tile2d_donor(GridDev g, Phys ph, const double *__restrict__ q, double *__r
     static_assert(TX_ * TY_ * TM_ >= 256, "the donor body needs 256 threads");
     extern __shared__ double sh[];
     const int ntile = ntx * nty;
-    if ((int)blockIdx.x < ntile) {
-        const int tile = xcd_tile(blockIdx.x, ntile);
+    const int nride = b.nchunk * a.nj, npad = (nride + 7) / 8 * 8;
+    if ((int)blockIdx.x >= npad) {
+        const int tile = xcd_tile(blockIdx.x - npad, ntile);
         rhs_tile2d_body<SBP, CART, TX_, TY_, TM_>(g, ph, q, F, cb, (tile % ntx) * TX_, (tile / ntx) * TY_);
-    } else {
-        const int d = (int)blockIdx.x - ntile;
+    } else if ((int)blockIdx.x < nride) {
+        const int d = (int)blockIdx.x;
         donor_block_body<2, SBP, 2, 1>(a, b, d % b.nchunk, d / b.nchunk, sh);
     }
 }
@@ -1759,7 +1777,7 @@ static hipError_t tile2d_donor_shape(const GridDev &g, int sbp, const Phys &ph, 
         return hipErrorInvalidValue;
     } else {
         int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY;
-        dim3 grid(ntx * nty + b.nchunk * a.nj), blk(TX * TY * TM);
+        dim3 grid(ntx * nty + (b.nchunk * a.nj + 7) / 8 * 8), blk(TX * TY * TM);
         if (sbp == 21 && g.cartesian)
             hipLaunchKernelGGL((k_rhs_tile2d_donor<21, 1, TX, TY, TM>), grid, blk, lds, st, g, ph, q, F, cb, ntx, nty,
                                a, b);
