@@ -77,16 +77,16 @@ struct DonorLink {
 
 // Receivers of a link cut into chunks of rpc consecutive receivers (rpc * S
 // = 256 entries), one workgroup per (chunk, slot): the chunk's distinct donor
-// points upts[ustart[c] .. ustart[c+1]) (sorted), each entry's index among
-// them (eloc, receiver-major), the points their gradient stencils read,
-// cpts[cstart[c] .. cstart[c+1]) (sorted; used when the state is an
-// extrapolant), and per distinct donor point 1 + 4 dim positions in that
-// list (bpos, same indexing as upts times 1 + 4 dim): the point, then its
-// stencil in the order the gradient reads it (-1 past a short row).
+// points upts[c * maxu + u] (sorted, -1 past the chunk's count), each entry's
+// index among them (eloc, receiver-major), the points their gradient stencils
+// read, cpts[c * maxc + i] (sorted, -1 past the count; used when the state is
+// an extrapolant), and per distinct donor point 1 + 4 dim positions in that
+// list (bpos[(c * maxu + u) * (1 + 4 dim) + t]): the point, then its stencil
+// in the order the gradient reads it (-1 past a short row).
 // Dynamic LDS: maxu * RB + maxc * nv doubles, and maxu * (1 + 4 dim) int16
 // when extrapolating.
 struct DonorBlocks {
-    const int32_t *ustart, *upts, *cstart, *cpts;
+    const int32_t *upts, *cpts;
     const int16_t *eloc, *bpos;
     int nchunk, rpc, maxu, maxc;
 };

@@ -825,7 +825,7 @@ __device__ __forceinline__ int wrap1(int i, int n)
 }
 
 // the work of one workgroup: the tile with corner (x0, y0) of grid g
-template <int SBP, int CART, int TX_, int TY_, int TM_>
+template <int SBP, int CART, int TX_, int TY_, int TM_, bool NOEARLY = false>
 __device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph, const double *__restrict__ q,
                                                 double *__restrict__ F, const Combine &cb, int x0, int y0)
 {
@@ -852,7 +852,7 @@ __device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph
     const int64_t po = inside ? (int64_t)gyo * nx + gxo : 0;
     // (small, latency-bound tiles only: on large tiles the long live ranges
     // cost more occupancy than the early loads save)
-    constexpr bool EARLY = TX_ * TY_ <= 128;
+    constexpr bool EARLY = TX_ * TY_ <= 128 && !NOEARLY;
     constexpr int HV = EARLY ? MAXH - 1 : 1;
     double hq[4], hv[HV][4];
     if constexpr (EARLY) {
@@ -1331,9 +1331,10 @@ __device__ __forceinline__ void donor_block_body(const DonorLink &a, const Donor
         }
     const int64_t N = a.g.npts;
     // loads that depend on nothing the work computes are issued first: this
-    // lane's receiver entry (weight, row of its donor point), the chunk's
-    // ranges, then this lane's distinct donor point (a chunk has at most 256,
-    // one per lane) and its stencil positions
+    // lane's receiver entry (weight, row of its donor point), its distinct
+    // donor point (a chunk has at most 256, one per lane) with its stencil
+    // positions, and the chunk's closure points (lists padded to maxu and
+    // maxc per chunk, -1 past a chunk's count)
     const int kk = tid / a.S, e = tid - kk * a.S;
     const int64_t k = (int64_t)ch * b.rpc + kk;
     const bool ok = tid < NT && kk < b.rpc && k < a.nrecv;
@@ -1344,30 +1345,36 @@ __device__ __forceinline__ void donor_block_body(const DonorLink &a, const Donor
         w_ent = a.w[ent];
         el_ent = b.eloc[ent];
     }
-    const int u0 = b.ustart[ch], nu = b.ustart[ch + 1] - u0;
-    const bool own_u = tid < NT && tid < nu;
-    const int64_t p_own = own_u ? b.upts[u0 + tid] : 0;
-    int c0 = 0, nc = 0;
+    const bool lane_u = tid < NT && tid < b.maxu;
+    const int64_t p_own = lane_u ? b.upts[(int64_t)ch * b.maxu + tid] : -1;
+    const bool own_u = p_own >= 0;
     if constexpr (EXT) {
-        c0 = b.cstart[ch];
-        nc = b.cstart[ch + 1] - c0;
         int16_t bp[KP];
 #pragma unroll
-        for (int r = 0; r < KP; ++r) bp[r] = own_u ? b.bpos[(size_t)(u0 + tid) * KP + r] : (int16_t)0;
+        for (int r = 0; r < KP; ++r) bp[r] = lane_u ? b.bpos[((int64_t)ch * b.maxu + tid) * KP + r] : (int16_t)0;
         const int mh = a.m;
+        const int nc = b.maxc;
+        const int32_t *cp = b.cpts + (int64_t)ch * nc;
         // batches of XB items per thread: every load of a batch is issued
         // before the first sum
         constexpr int XB = 4;
         for (int base = 0; base < nc * NV; base += NT * XB) {
             double ly[XB], lh[XB][MAXH];
             int64_t el[XB];
+            int32_t pt[XB];
+#pragma unroll
+            for (int r = 0; r < XB; ++r) {
+                const int i = base + r * NT + tid;
+                pt[r] = -1;
+                if (tid < NT && i < nc * NV) pt[r] = cp[i - (i / nc) * nc];
+            }
 #pragma unroll
             for (int r = 0; r < XB; ++r) {
                 const int i = base + r * NT + tid;
                 el[r] = -1;
-                if (tid < NT && i < nc * NV) {
-                    const int v = i / nc, ii = i - v * nc;
-                    el[r] = (int64_t)v * N + b.cpts[c0 + ii];
+                if (pt[r] >= 0) {
+                    const int v = i / nc;
+                    el[r] = (int64_t)v * N + pt[r];
                     ly[r] = y[el[r]];
 #pragma unroll
                     for (int hh = 0; hh < MAXH; ++hh)
@@ -1501,22 +1508,24 @@ __global__ void __launch_bounds__(256) k_donor_blocks(const LinkJob *__restrict_
 // touches (another grid's mid-step data, gathered right after that grid
 // evaluated at the same micro-time): workgroups below ntx * nty take the
 // tiles (XCD-ordered as in k_rhs_tile2d), the rest take (chunk, slot) pairs
-// of the link with the first 256 threads.  One launch less per pair.
+// of the link with the first 256 threads.  One launch less per pair.  The
+// tiles here request their state and history values in the epilogue, which
+// keeps the kernel within 128 VGPRs: two workgroups fit a CU, so the donor
+// workgroups run beside the tiles rather than after them.
 template <int SBP, int CART, int TX_, int TY_, int TM_>
-__global__ void __launch_bounds__(TX_ * TY_ * TM_, 2)
+__global__ void __launch_bounds__(TX_ * TY_ * TM_, 4)
 k_rhs_tile2d_donor(GridDev g, Phys ph, const double *__restrict__ q, double *__restrict__ F, Combine cb, int ntx,
                    int nty, DonorLink a, DonorBlocks b)
 {
     static_assert(TX_ * TY_ * TM_ >= 256, "the donor body needs 256 threads");
     extern __shared__ double sh[];
     const int ntile = ntx * nty;
-    const int nride = b.nchunk * a.nj, npad = (nride + 7) / 8 * 8;
-    if ((int)blockIdx.x >= npad) {
-        const int tile = xcd_tile(blockIdx.x - npad, ntile);
-        rhs_tile2d_body<SBP, CART, TX_, TY_, TM_>(g, ph, q, F, cb, (tile % ntx) * TX_, (tile / ntx) * TY_);
-    } else if ((int)blockIdx.x < nride) {
-        const int d = (int)blockIdx.x;
-        donor_block_body<2, SBP, 2, 1>(a, b, d % b.nchunk, d / b.nchunk, sh);
+    if ((int)blockIdx.x < ntile) {
+        const int tile = xcd_tile(blockIdx.x, ntile);
+        rhs_tile2d_body<SBP, CART, TX_, TY_, TM_, true>(g, ph, q, F, cb, (tile % ntx) * TX_, (tile / ntx) * TY_);
+    } else {
+        const int d = (int)blockIdx.x - ntile;
+        if (d < b.nchunk * a.nj) donor_block_body<2, SBP, 2, 1>(a, b, d % b.nchunk, d / b.nchunk, sh);
     }
 }
 
@@ -1777,7 +1786,7 @@ static hipError_t tile2d_donor_shape(const GridDev &g, int sbp, const Phys &ph, 
         return hipErrorInvalidValue;
     } else {
         int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY;
-        dim3 grid(ntx * nty + (b.nchunk * a.nj + 7) / 8 * 8), blk(TX * TY * TM);
+        dim3 grid(ntx * nty + b.nchunk * a.nj), blk(TX * TY * TM);
         if (sbp == 21 && g.cartesian)
             hipLaunchKernelGGL((k_rhs_tile2d_donor<21, 1, TX, TY, TM>), grid, blk, lds, st, g, ph, q, F, cb, ntx, nty,
                                a, b);

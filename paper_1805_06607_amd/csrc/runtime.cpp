@@ -71,9 +71,9 @@ struct Link {
     // chunked form for the one-launch donor kernel (mrk::DonorBlocks)
     bool blk = false;
     int nchunk = 0, rpc = 0, maxu = 0, maxc = 0;
-    std::vector<int32_t> bus, bup, bcs, bcp;
+    std::vector<int32_t> bup, bcp;
     std::vector<int16_t> bel, bpos;
-    int32_t *bus_d = nullptr, *bup_d = nullptr, *bcs_d = nullptr, *bcp_d = nullptr;
+    int32_t *bup_d = nullptr, *bcp_d = nullptr;
     int16_t *bel_d = nullptr, *bpos_d = nullptr;
 };
 
@@ -419,24 +419,24 @@ void build_closure(const mr_ctx *c, int d, GridHost &D)
 }
 
 // chunks of rpc = 256 / S consecutive receivers: distinct donor points,
-// each entry's index among them, and the points their gradient stencils read
+// each entry's index among them, and the points their gradient stencils read;
+// every chunk's lists padded to the longest chunk's (-1 past its end), so that
+// a workgroup finds its chunk's lists without first reading their bounds
 void build_blocks(const mr_ctx *c, Link &L)
 {
     const GridHost &D = c->G[L.dg];
     const int S = c->S;
+    const int kp = 1 + 4 * D.dim;
     L.rpc = 256 / S;
     L.nchunk = (int)((L.n + L.rpc - 1) / L.rpc);
-    L.bus.assign(1, 0);
-    L.bcs.assign(1, 0);
-    L.bup.clear();
-    L.bcp.clear();
     L.bel.assign((size_t)L.n * S, 0);
-    L.bpos.clear();
     L.maxu = L.maxc = 0;
+    std::vector<std::vector<int32_t>> Us(L.nchunk), Cs(L.nchunk);
+    std::vector<std::vector<int16_t>> Ps(L.nchunk);
     std::vector<int> off;
     for (int ch = 0; ch < L.nchunk; ++ch) {
         int64_t r0 = (int64_t)ch * L.rpc, r1 = std::min<int64_t>(L.n, r0 + L.rpc);
-        std::vector<int32_t> U;
+        std::vector<int32_t> &U = Us[ch];
         for (int64_t r = r0; r < r1; ++r)
             for (int e = 0; e < S; ++e) U.push_back(c->ept[(size_t)(L.first + r) * S + e]);
         std::sort(U.begin(), U.end());
@@ -446,7 +446,7 @@ void build_blocks(const mr_ctx *c, Link &L)
                 int32_t q = c->ept[(size_t)(L.first + r) * S + e];
                 L.bel[(size_t)r * S + e] = (int16_t)(std::lower_bound(U.begin(), U.end(), q) - U.begin());
             }
-        std::vector<int32_t> C;
+        std::vector<int32_t> &C = Cs[ch];
         for (int32_t p : U) {
             C.push_back(p);
             int ic[3] = {(int)(p % D.n[0]), (int)((p / D.n[0]) % D.n[1]), (int)(p / ((int64_t)D.n[0] * D.n[1]))};
@@ -463,7 +463,6 @@ void build_blocks(const mr_ctx *c, Link &L)
         C.erase(std::unique(C.begin(), C.end()), C.end());
         // per distinct point: its position in C, then its stencil's, in the
         // order the device gradient reads them
-        const int kp = 1 + 4 * D.dim;
         auto at = [&](int64_t q) { return (int16_t)(std::lower_bound(C.begin(), C.end(), (int32_t)q) - C.begin()); };
         for (int32_t p : U) {
             std::vector<int16_t> row(kp, (int16_t)-1);
@@ -478,14 +477,18 @@ void build_blocks(const mr_ctx *c, Link &L)
                     row[t++] = at(p + (int64_t)(j - ic[m]) * D.stride[m]);
                 }
             }
-            L.bpos.insert(L.bpos.end(), row.begin(), row.end());
+            Ps[ch].insert(Ps[ch].end(), row.begin(), row.end());
         }
         L.maxu = std::max(L.maxu, (int)U.size());
         L.maxc = std::max(L.maxc, (int)C.size());
-        L.bup.insert(L.bup.end(), U.begin(), U.end());
-        L.bcp.insert(L.bcp.end(), C.begin(), C.end());
-        L.bus.push_back((int32_t)L.bup.size());
-        L.bcs.push_back((int32_t)L.bcp.size());
+    }
+    L.bup.assign((size_t)L.nchunk * L.maxu, -1);
+    L.bcp.assign((size_t)L.nchunk * L.maxc, -1);
+    L.bpos.assign((size_t)L.nchunk * L.maxu * kp, (int16_t)-1);
+    for (int ch = 0; ch < L.nchunk; ++ch) {
+        std::copy(Us[ch].begin(), Us[ch].end(), L.bup.begin() + (size_t)ch * L.maxu);
+        std::copy(Cs[ch].begin(), Cs[ch].end(), L.bcp.begin() + (size_t)ch * L.maxc);
+        std::copy(Ps[ch].begin(), Ps[ch].end(), L.bpos.begin() + (size_t)ch * L.maxu * kp);
     }
     // one workgroup's LDS; stencils of 64 entries (3D) keep the two-launch form
     L.blk = S <= 16 && mrk::donor_block_lds(D.dim, L.maxu, L.maxc) <= 64 * 1024;
@@ -537,8 +540,6 @@ size_t layout(mr_ctx *c, char *base)
     for (Link &L : c->links) {
         L.upts_d = cv.take<int32_t>(L.upts.size() + 1);
         L.vals_d = cv.take<double>((size_t)c->rmax * L.upts.size() * RB + 1);
-        L.bus_d = cv.take<int32_t>(L.bus.size());
-        L.bcs_d = cv.take<int32_t>(L.bcs.size());
         L.bup_d = cv.take<int32_t>(L.bup.size() + 1);
         L.bcp_d = cv.take<int32_t>(L.bcp.size() + 1);
         L.bel_d = cv.take<int16_t>(L.bel.size() + 1);
@@ -643,9 +644,7 @@ bool use_blocks(const mr_ctx *c, const Link &L) { return c->donor_blocks && L.bl
 mrk::DonorBlocks link_blocks(const Link &L)
 {
     mrk::DonorBlocks b{};
-    b.ustart = L.bus_d;
     b.upts = L.bup_d;
-    b.cstart = L.bcs_d;
     b.cpts = L.bcp_d;
     b.eloc = L.bel_d;
     b.bpos = L.bpos_d;
@@ -2656,8 +2655,6 @@ int bind_at(mr_ctx *c, void *dev)
     }
     for (Link &L : c->links) {
         HIPCHK(c, hipMemcpyAsync(L.upts_d, L.upts.data(), L.upts.size() * 4, hipMemcpyHostToDevice, c->st));
-        HIPCHK(c, hipMemcpyAsync(L.bus_d, L.bus.data(), L.bus.size() * 4, hipMemcpyHostToDevice, c->st));
-        HIPCHK(c, hipMemcpyAsync(L.bcs_d, L.bcs.data(), L.bcs.size() * 4, hipMemcpyHostToDevice, c->st));
         if (!L.bup.empty())
             HIPCHK(c, hipMemcpyAsync(L.bup_d, L.bup.data(), L.bup.size() * 4, hipMemcpyHostToDevice, c->st));
         if (!L.bcp.empty())
