@@ -529,7 +529,13 @@ def run_gpu(args):
     mr = System(wl)
     h, H = mr.timestep()
     mr.start(0.0)
-    tiles = mr.autotune(reps=20)
+    if args.tile_shapes:
+        # fixed shapes (counter runs: the profiler's own overhead would sway the autotuner)
+        for g, sh in enumerate(int(x) for x in args.tile_shapes.split(",")):
+            mr.set_tile_shape(g, sh)
+        tiles = [mr.tile_shape(g) for g in range(mr.ngrids)]
+    else:
+        tiles = mr.autotune(reps=20)
     log(f"tile shapes (shape, tx, ty, threads per output): {tiles}")
     n_act = active_counts(mr)
     rates = [g.rate for g in wl.grids]
@@ -803,6 +809,8 @@ def main():
     ap.add_argument("--adj-macrosteps", type=int, default=200)
     ap.add_argument("--adj-snapshots", type=int, default=20)
     ap.add_argument("--adj-fd-eps", type=float, default=1e-3)
+    ap.add_argument("--tile-shapes", default="",
+                    help="comma-separated tile shape per grid of the cylinder case instead of the autotuner's")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
