@@ -114,3 +114,26 @@ def test_tile_shape_table_without_device():
     lib = _lib.load()
     for bad in (-1, _lib.NUM_TILE_SHAPES):
         assert _lib.STATUS[lib.mr_tile_shape_info(bad, None, None, None)] == "MR_ERR_ARG"
+
+
+def test_c_only_caller_sets_up_a_system(tmp_path):
+    """A plain C program (tests/c_abi/setup_cylinder.c) builds a cylinder-like
+    overset system through the ABI alone, the donor search being the
+    library's own (no locate callback): every receiver gets a donor, its
+    weights sum to one and reproduce its position, and mr_finalize accepts
+    the system.  Host only: no device."""
+    import shutil
+    import subprocess
+    from paper_1805_06607_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    exe = str(tmp_path / "setup_cylinder")
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    subprocess.run([cc, "-std=c11", "-O1", "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "c_abi", "setup_cylinder.c"), "-o", exe,
+                    "-L", libdir, "-lmrab", "-Wl,-rpath," + libdir, "-lm"], check=True)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    words = out.stdout.split()
+    assert words[0] == "ok" and int(words[1]) > 0 and int(words[2]) > 0 and int(words[3]) > 0, out.stdout
