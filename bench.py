@@ -1,7 +1,7 @@
 """Benchmark: multi-rate vs single-rate Adams-Bashforth on the cylinder-like
 overset workload, one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-equal-error]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-equal-error] [--no-3d] [--tile-shapes S0,S1]
 
 Workload (synthetic stand-in for the paper's cylinder case): a 512 x 512
 Cartesian background on [-20, 20]^2 with far-field faces and a hole r < 2, and
