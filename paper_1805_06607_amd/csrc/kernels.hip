@@ -865,6 +865,23 @@ __device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph
                 for (int v = 0; v < 4; ++v) hv[j][v] = cb.hist[j][v * N + po];
             }
     }
+    // NOEARLY (a kernel that must stay within 128 VGPRs): the same early
+    // requests for the state and the HE oldest history values, parked in LDS
+    // once the staging loads have landed instead of held in registers
+    constexpr bool ELDS = NOEARLY && TX_ * TY_ <= 128;
+    constexpr int HE = ELDS ? 3 : 1;
+    __shared__ double sE[ELDS ? 4 * (1 + HE) : 1][ELDS ? C::NO : 1];
+    double eq[4], eh[HE][4];
+    if constexpr (ELDS) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) eq[v] = inside ? q[v * N + po] : 0.0;
+#pragma unroll
+        for (int j = 0; j < HE; ++j)
+            if (j < cb.m - 1 && inside) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) eh[j][v] = cb.hist[j][v * N + po];
+            }
+    }
 
     // 1. stage: issue every load first
     double lq[C::NIT][4];
@@ -935,6 +952,18 @@ __device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph
             sP[3][cy][cx] = T;
             sC[0][cy][cx] = lc[it][0];
             sC[1][cy][cx] = lc[it][1];
+        }
+    }
+    if constexpr (ELDS) {
+        if (inside) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sE[v][tid] = eq[v];
+#pragma unroll
+            for (int j = 0; j < HE; ++j)
+                if (j < cb.m - 1) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) sE[4 + 4 * j + v][tid] = eh[j][v];
+                }
         }
     }
     __syncthreads();
@@ -1059,7 +1088,10 @@ __device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph
 
     // 3. epilogue
     if (!inside) return;
-    if constexpr (!EARLY) {
+    if constexpr (ELDS) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) hq[v] = sE[v][tid];
+    } else if constexpr (!EARLY) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) hq[v] = q[v * N + po];
     }
@@ -1145,6 +1177,7 @@ __device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph
                 if (j < cb.m - 1) {
                     double h;
                     if constexpr (EARLY) h = hv[j < HV ? j : 0][v];
+                    else if (ELDS && j < HE) h = sE[4 + 4 * (j < HE ? j : 0) + v][tid];
                     else h = cb.hist[j][v * N + p];
                     a2 = add_nc(a2, cb.c[j], h);
                 }
