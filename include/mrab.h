@@ -146,9 +146,12 @@ typedef int (*mr_locate_fn)(void *user, int grid, int64_t n, const double *x, do
  * direction).  Receivers register grid by grid, per grid donor by donor in
  * priority order, ascending point order within a pair (mr_get_overset reads
  * them back).  Host only.
- * Errors: MR_ERR_ARG (width, stencil above 64 points), MR_ERR_STATE (after
- * mr_finalize, receivers already registered), MR_ERR_SETUP (a receiver
- * without a donor, the callback failed). */
+ * width^dim must be a power of two of at most 64 (widths 1, 2, 4; 8 in 2D).
+ * On an error the stencils registered before it stay: set up a new context
+ * to retry.
+ * Errors: MR_ERR_ARG (width), MR_ERR_STATE (after mr_finalize, receivers
+ * already registered), MR_ERR_SETUP (a receiver without a donor, the
+ * callback failed). */
 int mr_assemble_overset(mr_ctx *ctx, int width, const int *priority, mr_locate_fn locate, void *user);
 
 /* The registered donor stencils of grid's receivers, in row order: with every

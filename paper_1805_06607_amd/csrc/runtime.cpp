@@ -2408,7 +2408,7 @@ int mr_assemble_overset(mr_ctx *c, int W, const int *priority, mr_locate_fn loca
     const int dim = c->P.dim;
     int S = 1;
     for (int d = 0; d < dim; ++d) S *= W;
-    if (S > 64) return fail(c, MR_ERR_ARG, "stencil of more than 64 points");
+    if (S > 64 || (S & (S - 1))) return fail(c, MR_ERR_ARG, "width^dim must be a power of two of at most 64");
     for (const GridHost &g : c->G)
         for (int64_t p = 0; p < g.npts; ++p)
             if (g.recv_idx[p] >= 0) return fail(c, MR_ERR_STATE, "receivers already registered");

@@ -295,6 +295,7 @@ def test_assembly_errors():
     try:
         prio = (ctypes.c_int * 2)(0, 1)
         assert _lib.STATUS[lib.mr_assemble_overset(h.ctx, 4, prio, _lib.LOCATE_FN(), None)] == "MR_ERR_STATE"
+        assert _lib.STATUS[lib.mr_assemble_overset(h.ctx, 3, prio, _lib.LOCATE_FN(), None)] == "MR_ERR_ARG"
     finally:
         lib.mr_destroy(h.ctx)
     # the background's hole grown past the patch: no receiver has a donor
