@@ -883,6 +883,12 @@ __device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph
             }
     }
 
+    // small tiles with early requests: a receiver's donor row (interface SAT
+    // data) is requested once every staging load has been issued (its row
+    // index first); other tiles read it in the epilogue
+    constexpr bool RBE = EARLY;
+    const int rrow = RBE && inside && g.recv_idx ? g.recv_idx[po] : -1;
+
     // 1. stage: issue every load first
     double lq[C::NIT][4];
     int8_t lc[C::NIT][2];
@@ -908,6 +914,13 @@ __device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph
             }
         }
     }
+    double rbv[RBE ? 10 : 1];
+    auto rbload = [&]() {
+        if constexpr (RBE) {
+#pragma unroll
+            for (int t = 0; t < 10; ++t) rbv[t] = rrow >= 0 ? g.recv[(int64_t)rrow * 10 + t] : 0.0;
+        }
+    };
     if constexpr (!CART) {
         constexpr int MIT = (MN + NT - 1) / NT;
         double lm[MIT][5];
@@ -923,6 +936,7 @@ __device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph
 #pragma unroll
             for (int kk = 0; kk < 5; ++kk) lm[it][kk] = ok ? g.metric[kk * N + p] : 0.0;
         }
+        rbload();
 #pragma unroll
         for (int it = 0; it < MIT; ++it) {
             int e = tid + it * NT;
@@ -931,6 +945,8 @@ __device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph
                 for (int kk = 0; kk < 5; ++kk) sM[kk][e] = lm[it][kk];
             }
         }
+    } else {
+        rbload();
     }
 #pragma unroll
     for (int it = 0; it < C::NIT; ++it) {
@@ -1107,11 +1123,16 @@ __device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph
         for (int v = 0; v < 4; ++v) r[v] = -J * acc[v];
         if (((cx0 >> 4) & 3) | ((cy0 >> 4) & 3)) {
             double qp[4] = {hq[0], hq[1], hq[2], hq[3]};
-            double gr[3][2];
-            grad_at(cxo, cyo, gr);
-            double uu[2] = {sP[1][cyo][cxo], sP[2][cyo][cxo]};
-            double Fv[2][3];
-            viscous_flux<2>(ph, uu, gr, Fv);
+            // the viscous flux enters the interface and far-field penalties
+            // only (a wall point's penalty has no flux term)
+            const int b0 = (cx0 >> 4) & 3, b1 = (cy0 >> 4) & 3;
+            double Fv[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+            if (b0 == 1 || b0 == 2 || b1 == 1 || b1 == 2) {
+                double gr[3][2];
+                grad_at(cxo, cyo, gr);
+                double uu[2] = {sP[1][cyo][cxo], sP[2][cyo][cxo]};
+                viscous_flux<2>(ph, uu, gr, Fv);
+            }
             for (int m = 0; m < 2; ++m) {
                 int c = m == 0 ? cx0 : cy0;
                 int bc = (c >> 4) & 3;
@@ -1133,7 +1154,7 @@ __device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph
 #pragma unroll
                 for (int v = 1; v < 4; ++v) s2[v] = kap[0] * Fv[0][v - 1] + kap[1] * Fv[1][v - 1];
                 if (bc == 1) {
-                    const double *rb = g.recv + (int64_t)g.recv_idx[p] * 10;
+                    const double *rb = RBE ? rbv : g.recv + (int64_t)g.recv_idx[p] * 10;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) { dQ[v] = qp[v] - rb[v]; dV[v] = dQ[v]; }
 #pragma unroll
@@ -1144,11 +1165,11 @@ __device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph
                     for (int v = 0; v < 4; ++v) { dQ[v] = qp[v] - ph.q_inf[v]; dV[v] = dQ[v]; }
                     sigI = ph.sig_bc;
                 } else {
-                    double kn = sqrt(k2);
-                    double mn = (qp[1] * kap[0] + qp[2] * kap[1]) / kn;
+                    // twice the normal momentum along the unit normal kappa / |kappa|
+                    double tm = 2.0 * (qp[1] * kap[0] + qp[2] * kap[1]) / k2;
                     dQ[0] = 0.0; dV[0] = 0.0;
-                    dQ[1] = 2.0 * mn * kap[0] / kn; dV[1] = qp[1];
-                    dQ[2] = 2.0 * mn * kap[1] / kn; dV[2] = qp[2];
+                    dQ[1] = tm * kap[0]; dV[1] = qp[1];
+                    dQ[2] = tm * kap[1]; dV[2] = qp[2];
                     dQ[3] = 0.0; dV[3] = qp[3] - qp[0] * ph.T_wall / gm1;
                     sigI = ph.sig_bc;
                     sig1 = ph.wall_visc * ph.mu * k2 / ph.Re;
