@@ -184,15 +184,16 @@ __device__ __forceinline__ void sat_point(const GridDev &g, const Phys &ph, cons
                 for (int v = 0; v < NV; ++v) { dQ[v] = qp[v] - ph.q_inf[v]; dV[v] = dQ[v]; }
                 sigI = ph.sig_bc;
             } else {
-                // wall: reflected normal momentum (inviscid), rest at T_wall (viscous)
-                double kn = sqrt(k2), mn = 0.0;
+                // wall: reflected normal momentum (inviscid), rest at T_wall
+                // (viscous); twice the normal momentum along kappa / |kappa|
+                double mn = 0.0;
 #pragma unroll
                 for (int i = 0; i < DIM; ++i) mn += qp[1 + i] * kap[i];
-                mn /= kn;
+                const double tm = 2.0 * mn / k2;
                 dQ[0] = 0.0;
                 dV[0] = 0.0;
 #pragma unroll
-                for (int i = 0; i < DIM; ++i) { dQ[1 + i] = 2.0 * mn * kap[i] / kn; dV[1 + i] = qp[1 + i]; }
+                for (int i = 0; i < DIM; ++i) { dQ[1 + i] = tm * kap[i]; dV[1 + i] = qp[1 + i]; }
                 dQ[NV - 1] = 0.0;
                 dV[NV - 1] = qp[NV - 1] - qp[0] * ph.T_wall / (ph.gamma - 1.0);
                 sigI = ph.sig_bc;
@@ -1166,7 +1167,10 @@ __device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph
                     sigI = ph.sig_bc;
                 } else {
                     // twice the normal momentum along the unit normal kappa / |kappa|
-                    double tm = 2.0 * (qp[1] * kap[0] + qp[2] * kap[1]) / k2;
+                    double mn = 0.0;
+                    mn += qp[1] * kap[0];
+                    mn += qp[2] * kap[1];
+                    const double tm = 2.0 * mn / k2;
                     dQ[0] = 0.0; dV[0] = 0.0;
                     dQ[1] = tm * kap[0]; dV[1] = qp[1];
                     dQ[2] = tm * kap[1]; dV[2] = qp[2];
