@@ -24,6 +24,9 @@ def _say(*a):
 CASES = {
     "vortex_box": lambda: workloads.vortex_box(),
     "cylinder_small": lambda: workloads.cylinder(nbg=96, ntheta=64, nr=32, half=6.0),
+    # extended history (m = 6 > n = 4): more history values than a riding
+    # launch's tiles park in LDS
+    "cylinder_small_m6": lambda: workloads.cylinder(nbg=96, ntheta=64, nr=32, half=6.0, hist_len=6),
     "mms_box_42": lambda: workloads.mms_box(48, viscous=True, sbp=42),
     "torus_curvilinear": lambda: workloads.periodic_curvilinear(40, 36),
     "omesh_freestream": lambda: workloads.omesh_freestream(),
@@ -118,7 +121,7 @@ def _run_both(wl, nmacro, options=None):
 
 
 @pytest.mark.parametrize("mode", list(DONOR_MODES))
-@pytest.mark.parametrize("case", ["vortex_box", "cylinder_small"])
+@pytest.mark.parametrize("case", ["vortex_box", "cylinder_small", "cylinder_small_m6"])
 def test_mrab_parity_100_macrosteps(torch, case, mode):
     wl = CASES[case]()
     _say("mrab parity", case, mode)
@@ -293,7 +296,7 @@ def test_multi_stream_bitwise(torch, case):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("case", ["vortex_box", "cylinder_small"])
+@pytest.mark.parametrize("case", ["vortex_box", "cylinder_small", "cylinder_small_m6"])
 @pytest.mark.parametrize("host_shape", [None, 1])
 def test_ride_donors_bitwise(torch, case, host_shape):
     """A slow grid's mid-step donor data launched inside the next same-time
