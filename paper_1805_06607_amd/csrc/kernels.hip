@@ -1481,7 +1481,11 @@ __device__ __forceinline__ void donor_block_body(const DonorLink &a, const Donor
         int ic[3];
         coords(a.g, p, ic);
         double gr[DIM + 1][DIM];
-        if constexpr (CART == 2) {          // grid kind chosen per link at run time
+        if constexpr (!EXT && DIM == 2) {
+            // current-time 2D links: the whole stencil requested at once
+            const bool cart = CART == 2 ? a.g.cartesian : CART == 1;
+            gradient_window<DIM, SBP>(a.g, p, ic, cart, a.ph.gamma - 1.0, y, qp, gr);
+        } else if constexpr (CART == 2) {   // grid kind chosen per link at run time
             if (a.g.cartesian)
                 gradient<DIM, SBP, 1>(a.g, p, ic, a.ph.gamma - 1.0, qload, gr);
             else

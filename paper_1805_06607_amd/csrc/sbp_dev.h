@@ -108,6 +108,44 @@ __device__ __forceinline__ void load_q(const double *q, int64_t N, int64_t p, do
     for (int v = 0; v < DIM + 2; ++v) out[v] = q[v * N + p];
 }
 
+// metric terms of point p for grad_cart: M_mj row-major, then J
+// (curvilinear grids only)
+template <int DIM, int CART>
+__device__ __forceinline__ void load_metric(const GridDev &g, int64_t p, double *met)
+{
+    if constexpr (!CART) {
+        const int64_t N = g.npts;
+        met[DIM * DIM] = g.metric[(int64_t)(DIM * DIM) * N + p];
+#pragma unroll
+        for (int m = 0; m < DIM * DIM; ++m) met[m] = g.metric[(int64_t)m * N + p];
+    }
+}
+
+// Cartesian gradient of (u_1..u_D, T) from its index-space derivatives
+// dxi[m] along each grid direction m (chain rule through the metric terms)
+template <int DIM, int CART>
+__device__ __forceinline__ void grad_cart(const GridDev &g, const Vec<DIM + 1> *dxi, const double *met,
+                                          double gr[DIM + 1][DIM])
+{
+    if constexpr (CART) {
+#pragma unroll
+        for (int a = 0; a <= DIM; ++a)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) gr[a][j] = g.inv_h[j] * dxi[j].v[a];
+    } else {
+        const double J = met[DIM * DIM];
+#pragma unroll
+        for (int a = 0; a <= DIM; ++a)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) {
+                double s = 0.0;
+#pragma unroll
+                for (int m = 0; m < DIM; ++m) s += met[m * DIM + j] * dxi[m].v[a];
+                gr[a][j] = J * s;
+            }
+    }
+}
+
 // gradient d(phi_a)/dx_j of (u_1..u_D, T) at point p; qload(idx, out[nv])
 template <int DIM, int SBP, int CART, class QL>
 __device__ __forceinline__ void gradient(const GridDev &g, int64_t p, const int *ic, double gm1, QL &&qload,
@@ -123,29 +161,53 @@ __device__ __forceinline__ void gradient(const GridDev &g, int64_t p, const int 
             return prim<DIM>(qq, gm1);
         });
     }
-    if constexpr (CART) {
+    double met[DIM * DIM + 1];
+    load_metric<DIM, CART>(g, p, met);
+    grad_cart<DIM, CART>(g, dxi, met, gr);
+}
+
+// the same gradient with every load issued before the first use: the
+// point's class rows, metric terms (when `cart` is false) and the states of
+// its whole +-R line windows (R = 1 for SBP 2-1, 3 for 4-2; positions past a
+// non-periodic end are clamped and never read by a row), qp being its own
+// state.  The rows are applied to the loaded windows exactly as gradient()
+// applies them.
+template <int DIM, int SBP>
+__device__ __forceinline__ void gradient_window(const GridDev &g, int64_t p, const int *ic, bool cart, double gm1,
+                                                const double *__restrict__ y, const double *qp,
+                                                double gr[DIM + 1][DIM])
+{
+    constexpr int NV = DIM + 2, RW = SBP == 21 ? 1 : 3;
+    const int64_t N = g.npts;
+    int row[DIM];
 #pragma unroll
-        for (int a = 0; a <= DIM; ++a)
+    for (int m = 0; m < DIM; ++m) row[m] = g.cls[m * N + p] & 15;
+    double met[DIM * DIM + 1];
+    if (!cart) load_metric<DIM, 0>(g, p, met);
+    double win[DIM][2 * RW][NV];
 #pragma unroll
-            for (int j = 0; j < DIM; ++j) gr[a][j] = g.inv_h[j] * dxi[j].v[a];
-    } else {
-        const int64_t N = g.npts;
-        double J = g.metric[(int64_t)(DIM * DIM) * N + p];
-        double M[DIM][DIM];
+    for (int m = 0; m < DIM; ++m)
 #pragma unroll
-        for (int m = 0; m < DIM; ++m)
+        for (int k = 0; k < 2 * RW; ++k) {
+            const int o = k < RW ? k - RW : k - RW + 1;
+            int jj = ic[m] + o;
+            if (g.periodic[m]) jj = jj < 0 ? jj + g.n[m] : (jj >= g.n[m] ? jj - g.n[m] : jj);
+            jj = jj < 0 ? 0 : (jj >= g.n[m] ? g.n[m] - 1 : jj);
+            const int64_t idx = p + (int64_t)(jj - ic[m]) * g.stride[m];
 #pragma unroll
-            for (int j = 0; j < DIM; ++j) M[m][j] = g.metric[(int64_t)(m * DIM + j) * N + p];
+            for (int v = 0; v < NV; ++v) win[m][k][v] = y[v * N + idx];
+        }
+    Vec<DIM + 1> dxi[DIM];
 #pragma unroll
-        for (int a = 0; a <= DIM; ++a)
-#pragma unroll
-            for (int j = 0; j < DIM; ++j) {
-                double s = 0.0;
-#pragma unroll
-                for (int m = 0; m < DIM; ++m) s += M[m][j] * dxi[m].v[a];
-                gr[a][j] = J * s;
-            }
-    }
+    for (int m = 0; m < DIM; ++m)
+        dxi[m] = dsbp<SBP, DIM + 1>(row[m], [&](int o) {
+            const double *qq = o == 0 ? qp : win[m][o < 0 ? o + RW : o + RW - 1];
+            return prim<DIM>(qq, gm1);
+        });
+    if (cart)
+        grad_cart<DIM, 1>(g, dxi, met, gr);
+    else
+        grad_cart<DIM, 0>(g, dxi, met, gr);
 }
 
 // Cartesian viscous flux vectors (components 1..nv-1) at a point
