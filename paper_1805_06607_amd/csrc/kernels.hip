@@ -155,7 +155,7 @@ __device__ __forceinline__ void sat_point(const GridDev &g, const Phys &ph, cons
 #pragma unroll
             for (int j = 0; j < DIM; ++j) k2 += kap[j] * kap[j];
             double dQ[NV], dV[NV], s2[NV];
-            double sigI, sig1 = ph.mu * k2 / (2.0 * ph.Re);
+            double sigI, sig1 = k2 * (ph.mu / (2.0 * ph.Re));
             bool use_s2 = true;
 #pragma unroll
             for (int v = 0; v < NV; ++v) s2[v] = 0.0;
@@ -195,9 +195,9 @@ __device__ __forceinline__ void sat_point(const GridDev &g, const Phys &ph, cons
 #pragma unroll
                 for (int i = 0; i < DIM; ++i) { dQ[1 + i] = tm * kap[i]; dV[1 + i] = qp[1 + i]; }
                 dQ[NV - 1] = 0.0;
-                dV[NV - 1] = qp[NV - 1] - qp[0] * ph.T_wall / (ph.gamma - 1.0);
+                dV[NV - 1] = qp[NV - 1] - qp[0] * (ph.T_wall / (ph.gamma - 1.0));
                 sigI = ph.sig_bc;
-                sig1 = ph.wall_visc * ph.mu * k2 / ph.Re;
+                sig1 = k2 * (ph.wall_visc * ph.mu / ph.Re);
                 use_s2 = false;
             }
             double KdQ[NV];
@@ -1150,7 +1150,7 @@ __device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph
                 }
                 double k2 = kap[0] * kap[0] + kap[1] * kap[1];
                 double dQ[4], dV[4], s2[4] = {0.0, 0.0, 0.0, 0.0};
-                double sigI, sig1 = ph.mu * k2 / (2.0 * ph.Re);
+                double sigI, sig1 = k2 * (ph.mu / (2.0 * ph.Re));
                 bool use_s2 = true;
 #pragma unroll
                 for (int v = 1; v < 4; ++v) s2[v] = kap[0] * Fv[0][v - 1] + kap[1] * Fv[1][v - 1];
@@ -1174,9 +1174,9 @@ __device__ __forceinline__ void rhs_tile2d_body(const GridDev &g, const Phys &ph
                     dQ[0] = 0.0; dV[0] = 0.0;
                     dQ[1] = tm * kap[0]; dV[1] = qp[1];
                     dQ[2] = tm * kap[1]; dV[2] = qp[2];
-                    dQ[3] = 0.0; dV[3] = qp[3] - qp[0] * ph.T_wall / gm1;
+                    dQ[3] = 0.0; dV[3] = qp[3] - qp[0] * (ph.T_wall / gm1);
                     sigI = ph.sig_bc;
-                    sig1 = ph.wall_visc * ph.mu * k2 / ph.Re;
+                    sig1 = k2 * (ph.wall_visc * ph.mu / ph.Re);
                     use_s2 = false;
                 }
                 double KdQ[4];

@@ -309,9 +309,10 @@ __device__ __forceinline__ void k_apply(double gamma, const double *q, const dou
     double dun = 0.0;
 #pragma unroll
     for (int i = 0; i < DIM; ++i) dun += du[i] * nh[i];
-    double ae = drho - dp / c2;
-    double ap = (dp + rho * c * dun) / (2.0 * c2);
-    double am = (dp - rho * c * dun) / (2.0 * c2);
+    const double ic2 = 1.0 / c2, hc2 = 0.5 * ic2;
+    double ae = drho - dp * ic2;
+    double ap = (dp + rho * c * dun) * hc2;
+    double am = (dp - rho * c * dun) * hc2;
     double l0 = U, lp = U + c * L, lm = U - c * L;
     double w0 = 0.5 * (fabs(l0) + sgn * l0);
     double wp = 0.5 * (fabs(lp) + sgn * lp);
